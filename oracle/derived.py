@@ -1,0 +1,133 @@
+"""Backward and double-backward contractions and the error metric.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+For a loss L that depends on the harmonics Y(x) of each point:
+
+* backward:        dL/dx_a = sum_k gY_k dY_{a,k}          (chain rule)
+* double backward: given v = dL'/d(dL/dx), the two partials of
+  L' = sum_a v_a sum_k gY_k dY_{a,k} are
+      dL'/dgY_k = sum_a v_a dY_{a,k}
+      dL'/dx_b  = sum_k gY_k sum_a v_a d^2Y_k/(dx_a dx_b)
+
+The paper names derivatives of any order (Sec. II, after Eq. iter-deri) and a
+custom backward that reuses the forward derivatives (Sec. III); the formulas
+above are plain calculus.  Second derivatives come from the exact
+polynomial derivatives of the definition tier.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from .definition import definition_eval_ld
+from .recurrence import real_sph
+
+LD = np.longdouble
+
+
+def backward(dY, gY):
+    """gxyz[n,a] = sum_k gY[n,k] dY[n,a,k], in longdouble."""
+    dY = np.asarray(dY).astype(LD)
+    gY = np.asarray(gY).astype(LD)
+    return np.einsum("nak,nk->na", dY, gY)
+
+
+def hessian_contract(H, gY, v):
+    """gxyz2[n,b] = sum_k gY[n,k] sum_a v[n,a] H[n,a,b,k]."""
+    H = np.asarray(H).astype(LD)
+    gY = np.asarray(gY).astype(LD)
+    v = np.asarray(v).astype(LD)
+    return np.einsum("nabk,nk,na->nb", H, gY, v)
+
+
+def double_backward(xyz, gY, v, l_max: int, normalize: bool):
+    """Return ``(ggY [N,K], gxyz2 [N,3])`` in longdouble.
+
+    Gradients come from the bulk tier, Hessians from the definition tier
+    (longdouble polynomials; use for l_max <= 12).
+    """
+    _, dY = real_sph(xyz, l_max, normalize, gradients=True)
+    _, _, H = definition_eval_ld(xyz, l_max, normalize, hessian=True)
+    v = np.asarray(v).astype(LD)
+    ggY = np.einsum("nak,na->nk", dY, v)
+    return ggY, hessian_contract(H, gY, v)
+
+
+# ------------------------------------------------------------ error metric
+def _ls(l_max):
+    return np.array([l for l in range(l_max + 1) for _ in range(2 * l + 1)], dtype=np.float64)
+
+
+def component_scales(xyz, l_max: int, normalize: bool):
+    """Per point and per column scales ``(s [N,K], g [N,K], h [N,K])``.
+
+    The addition theorem gives sum_m (Y_l^m)^2 = (2l+1)/(4 pi) (times r^2l for
+    the solid harmonics) and sum_m |grad Y_l^m|^2 = l(l+1)(2l+1)/(4 pi r^2)
+    (normalised) or l(2l+1)^2/(4 pi) r^(2l-2) (solid), so these are the natural
+    sizes of a column of degree l.  ``h`` (second derivatives) uses
+    (l+1)^2 sqrt((2l+1)/4pi) times r^(l-2) or r^-2.  l = 0 borrows the l = 1
+    gradient and Hessian scales (its exact derivatives are zero).
+    """
+    P = np.asarray(xyz, dtype=np.float64).reshape(-1, 3)
+    r = np.sqrt((P * P).sum(axis=1))
+    ls = _ls(l_max)
+    lg = np.maximum(ls, 1.0)
+    base = np.sqrt((2 * ls + 1) / (4 * math.pi))
+    gb = np.sqrt(lg * (lg + 1) * (2 * lg + 1) / (4 * math.pi)) if normalize else \
+        np.sqrt(lg * (2 * lg + 1) ** 2 / (4 * math.pi))
+    hb = (lg + 1) ** 2 * np.sqrt((2 * lg + 1) / (4 * math.pi))
+    with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+        if normalize:
+            rr = np.where(r > 0, r, 1.0)[:, None]
+            s = np.broadcast_to(base, (P.shape[0], ls.size)).copy()
+            g = gb[None, :] / rr
+            h = hb[None, :] / (rr * rr)
+        else:
+            s = base[None, :] * r[:, None] ** ls[None, :]
+            g = gb[None, :] * r[:, None] ** (lg[None, :] - 1)
+            h = hb[None, :] * r[:, None] ** (lg[None, :] - 2)
+    return s, g, h
+
+
+def _scaled(err, scale):
+    with np.errstate(divide="ignore", invalid="ignore"):
+        out = np.where(scale > 0, err / np.where(scale > 0, scale, 1.0), err)
+    return out
+
+
+def per_l_errors(Y, Yref, xyz, l_max: int, normalize: bool, kind: str = "Y",
+                 mask=None):
+    """Per-l max and RMS of the scaled error.
+
+    ``kind`` = "Y" for values [N,K]; "dY" for gradients [N,3,K].  Errors are
+    |a - ref| divided by the column scale of :func:`component_scales`, so a
+    value 10^-5 means "wrong in the 5th digit of a typical entry of degree l".
+    ``mask`` (bool [N]) restricts the points.  Returns ``(max[l], rms[l])``.
+    """
+    s, g, _ = component_scales(xyz, l_max, normalize)
+    A = np.asarray(Y, dtype=LD)
+    B = np.asarray(Yref, dtype=LD)
+    err = np.abs(A - B).astype(np.float64)
+    if kind == "Y":
+        e = _scaled(err, s)
+    elif kind == "dY":
+        e = _scaled(err, g[:, None, :])
+    else:
+        raise ValueError(kind)
+    # non-finite comparisons are errors unless both sides agree exactly
+    same = (A == B) | (np.isnan(A.astype(np.float64)) & np.isnan(B.astype(np.float64)))
+    e = np.where(same, 0.0, e)
+    e = np.where(np.isfinite(e), e, np.inf)
+    if mask is not None:
+        e = e[np.asarray(mask)]
+    mx = np.zeros(l_max + 1)
+    rms = np.zeros(l_max + 1)
+    for l in range(l_max + 1):
+        sl = e[..., l * l:(l + 1) * (l + 1)]
+        if sl.size == 0:
+            continue
+        mx[l] = sl.max()
+        rms[l] = math.sqrt(float(np.mean(sl.astype(np.float64) ** 2)))
+    return mx, rms
