@@ -1,0 +1,182 @@
+/*
+ * sph.h -- C ABI of libsph: real spherical harmonics and their Cartesian
+ * derivatives for batches of points on AMD Instinct MI355X (gfx950).
+ *
+ * The method is the Cartesian formulation of "Fast evaluation of spherical
+ * harmonics with sphericart" (arXiv:2302.08381): scaled (solid) harmonics
+ * r^l Y_l^m = F_l^{|m|} Q_l^{|m|}(z,r) {s_|m|, 1/sqrt2, c_m}
+ * (Eq. real-sh-cartesian) built from the polynomials Q_l^m, s_m, c_m of
+ * Eq. define-q by the recursions of Eqs. iter-q-alt and iter-sc, with the
+ * prefactors F_l^m (Eq. Flm, App. C) folded into Q, and the derivatives of
+ * Eq. iter-deri.  The normalised harmonics are the scaled ones evaluated at
+ * x/r with the chain rule applied to the derivatives (Sec. III).
+ *
+ * Conventions shared by every entry point
+ * --------------------------------------
+ * - Layout: contiguous row-major arrays.  For l_max = L there are
+ *   K = (L+1)^2 harmonics per point; column k = l*l + l + m with m running
+ *   from -l to l.  xyz is [n,3]; Y is [n,K]; dY is [n,3,K] (for each point,
+ *   the x, y and z derivative blocks of K values each).
+ * - Memory: every data pointer is a DEVICE pointer owned by the caller.
+ *   The library never allocates, frees or retains caller memory.  Outputs
+ *   must not overlap inputs.  16-byte aligned base pointers take the
+ *   vectorised store path; other alignments are accepted and slower.
+ * - Streams: `stream` is a hipStream_t passed as void* (NULL = the default
+ *   stream).  All work is enqueued asynchronously on it; nothing
+ *   synchronises the host except where stated.
+ * - Errors: arguments are validated on the host before anything is
+ *   enqueued.  On an error the call returns a non-zero sph_status_t, writes
+ *   nothing, and sph_last_error() holds a message (per host thread).
+ *   n = 0 (or n_env = 0) is valid and enqueues nothing.  A failed kernel
+ *   launch returns SPH_ERR_DEVICE.
+ * - Numerics: NaN/Inf inputs propagate to the outputs; they are not errors.
+ *   At r = 0 the scaled harmonics take their polynomial values; the
+ *   normalised ones return Y_0^0 = 1/(2 sqrt(pi)) and 0 for every other
+ *   value and derivative.  float32 kernels work in float32 throughout;
+ *   float64 kernels in float64.
+ * - Range: 0 <= l_max <= sph_max_lmax() (32).
+ */
+#ifndef SPH_H_
+#define SPH_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SPH_F32 = 0, /* float  */
+  SPH_F64 = 1  /* double */
+} sph_dtype_t;
+
+typedef enum {
+  SPH_OK = 0,
+  SPH_ERR_NULL = 1,    /* a required pointer is NULL while n > 0            */
+  SPH_ERR_INVALID = 2, /* n < 0, normalize not 0/1, bad dtype, bad option   */
+  SPH_ERR_LMAX = 3,    /* l_max < 0 or l_max > sph_max_lmax()               */
+  SPH_ERR_OFFSETS = 4, /* CSR offsets inconsistent (batched entry point)    */
+  SPH_ERR_DEVICE = 5   /* the HIP runtime reported an error                 */
+} sph_status_t;
+
+/* (l_max+1)^2, the number of harmonics per point; -1 if l_max < 0. */
+int32_t sph_num_components(int32_t l_max);
+
+/* Largest supported l_max (32). */
+int32_t sph_max_lmax(void);
+
+/* Static description of a status code.  Never NULL. */
+const char* sph_status_string(int32_t status);
+
+/* Detail of the last error on the calling host thread ("" if none). */
+const char* sph_last_error(void);
+
+/* Library version string, e.g. "1.0.0 gfx950". */
+const char* sph_version(void);
+
+/*
+ * sph_compute -- Y[n,K] for n points.
+ * Sec. II (Eqs. real-sh-cartesian, define-q, iter-q-alt, iter-sc) and
+ * Sec. III (normalised variant).
+ *   xyz        in  [n,3]  point coordinates
+ *   n          number of points (>= 0)
+ *   l_max      0..sph_max_lmax()
+ *   normalize  0: scaled harmonics r^l Y_l^m; 1: normalised Y_l^m
+ *   dtype      element type of xyz and Y
+ *   Y          out [n,K]
+ */
+int32_t sph_compute(const void* xyz, int64_t n, int32_t l_max, int32_t normalize,
+                    int32_t dtype, void* Y, void* stream);
+
+/*
+ * sph_compute_with_gradients -- Y[n,K] and dY[n,3,K] = dY/dxyz in one pass.
+ * Derivatives from Eq. iter-deri (Sec. II) with the product rule; for
+ * normalize = 1 the chain rule through x/r (Sec. III).
+ *   dY         out [n,3,K]; dY[i,a,k] = d Y[i,k] / d xyz[i,a]
+ * Other arguments as sph_compute.
+ */
+int32_t sph_compute_with_gradients(const void* xyz, int64_t n, int32_t l_max,
+                                   int32_t normalize, int32_t dtype, void* Y,
+                                   void* dY, void* stream);
+
+/*
+ * sph_backward -- grad_xyz[i,a] = sum_k grad_Y[i,k] * dY[i,a,k].
+ * The vector-Jacobian product of the forward, reusing the derivatives it
+ * stored (the custom backward of Sec. III).
+ *   dY         in  [n,3,K] as written by sph_compute_with_gradients
+ *   grad_Y     in  [n,K]   upstream gradient dL/dY
+ *   grad_xyz   out [n,3]
+ */
+int32_t sph_backward(const void* dY, const void* grad_Y, int64_t n, int32_t l_max,
+                     int32_t dtype, void* grad_xyz, void* stream);
+
+/*
+ * sph_double_backward -- the derivatives of L' = sum_{i,a} v[i,a] grad_xyz[i,a]
+ * where grad_xyz is the output of sph_backward:
+ *   grad_grad_Y[i,k] = sum_a v[i,a] dY[i,a,k]
+ *   grad_xyz2[i,b]   = sum_k grad_Y[i,k] sum_a v[i,a] d2Y[i,k]/dxyz_a dxyz_b
+ * Second derivatives come from applying Eq. iter-deri twice (Sec. II:
+ * derivatives of any order); they are formed in registers from xyz and
+ * never stored.
+ *   xyz            in  [n,3]
+ *   grad_Y         in  [n,K]
+ *   v              in  [n,3]  (upstream gradient of grad_xyz)
+ *   grad_grad_Y    out [n,K]  (may be NULL: not computed)
+ *   grad_xyz2      out [n,3]  (may be NULL: not computed)
+ */
+int32_t sph_double_backward(const void* xyz, const void* grad_Y, const void* v,
+                            int64_t n, int32_t l_max, int32_t normalize,
+                            int32_t dtype, void* grad_grad_Y, void* grad_xyz2,
+                            void* stream);
+
+/*
+ * sph_batched_compute -- many neighbour lists in one persistent launch.
+ * The points of n_env environments are concatenated (CSR): environment e
+ * owns rows offsets[e] .. offsets[e+1]-1 of xyz (Sec. III: the harmonics of
+ * the neighbours of each selected atom).  Every output follows the
+ * concatenated row order.  The launch is a persistent kernel replayed from a
+ * cached hipGraph; on the first call for a (dtype, l_max, normalize, outputs)
+ * combination the library times its launch variants on the caller's own
+ * buffers and keeps the fastest (the timing synchronises the host once).
+ *   xyz        in  [n_points,3]
+ *   offsets    in  int64 [n_env+1], DEVICE memory
+ *   n_env      number of environments (>= 0)
+ *   n_points   total number of points; must equal offsets[n_env]
+ *   Y          out [n_points,K]
+ *   dY         out [n_points,3,K]  (may be NULL: derivatives not stored)
+ *   grad_Y     in  [n_points,K]    (may be NULL: no backward)
+ *   grad_xyz   out [n_points,3]    (required iff grad_Y is given) --
+ *              the backward of sph_backward, fused into the same pass
+ *   status     out int32 [1], DEVICE memory (may be NULL).  The kernel
+ *              checks offsets[0] == 0, non-decreasing offsets and
+ *              offsets[n_env] == n_points, and writes SPH_OK or
+ *              SPH_ERR_OFFSETS there.  The outputs do not depend on the
+ *              offsets, so they are complete either way.
+ */
+int32_t sph_batched_compute(const void* xyz, const int64_t* offsets, int64_t n_env,
+                            int64_t n_points, int32_t l_max, int32_t normalize,
+                            int32_t dtype, void* Y, void* dY, const void* grad_Y,
+                            void* grad_xyz, int32_t* status, void* stream);
+
+/*
+ * sph_batched_set_options -- batched-path controls (process-wide).
+ *   use_graph  1: replay cached hipGraphs (default); 0: plain launches
+ *   autotune   1: time the launch variants on first use (default);
+ *              0: use the built-in defaults
+ */
+int32_t sph_batched_set_options(int32_t use_graph, int32_t autotune);
+
+/*
+ * sph_batched_get_config -- the launch variant chosen for a combination, as
+ * "variant=<i> blocks_per_cu=<b> budget=<e>" in buf (NUL-terminated, at most
+ * len bytes).  Returns SPH_ERR_INVALID if nothing was chosen yet.
+ */
+int32_t sph_batched_get_config(int32_t l_max, int32_t normalize, int32_t dtype,
+                               int32_t store_dY, int32_t with_backward,
+                               char* buf, int32_t len);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPH_H_ */

@@ -1,0 +1,33 @@
+"""Real spherical harmonics on MI355X (gfx950) after arXiv:2302.08381.
+
+The arithmetic lives in libsph.so (HIP kernels behind the C ABI of
+include/sph.h).  This package is its thin Python face:
+
+* :mod:`._native` -- one function per C entry point, same names
+  (``sph_compute``, ``sph_compute_with_gradients``, ``sph_backward``,
+  ``sph_double_backward``, ``sph_batched_compute`` ...), torch tensors in,
+  raw device pointers and the current HIP stream out;
+* :mod:`.autograd` -- ``spherical_harmonics`` / ``SphericalHarmonics`` with
+  first and second derivatives.
+
+Building: ``python -m paper_2302_08381_amd.build`` (hipcc, in-tree).
+"""
+from ._native import (  # noqa: F401
+    SphError,
+    library_path,
+    max_lmax,
+    num_components,
+    sph_backward,
+    sph_batched_compute,
+    sph_batched_get_config,
+    sph_batched_set_options,
+    sph_compute,
+    sph_compute_with_gradients,
+    sph_double_backward,
+    version,
+)
+from .autograd import (  # noqa: F401
+    SphericalHarmonics,
+    spherical_harmonics,
+    spherical_harmonics_with_gradients,
+)

@@ -1,0 +1,468 @@
+// C ABI of libsph (declared in include/sph.h): argument validation, kernel
+// dispatch, launch shapes, and the batched path's hipGraph cache and
+// launch-variant autotuner.
+#include "sph.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "sph_launch.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int32_t fail(int32_t code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int32_t ok() {
+  g_last_error.clear();
+  return SPH_OK;
+}
+
+int32_t device_fail(hipError_t e, const char* where) {
+  std::string m = std::string(where) + ": " + hipGetErrorString(e);
+  return fail(SPH_ERR_DEVICE, m);
+}
+
+size_t elem_size(int32_t dtype) { return dtype == SPH_F64 ? 8 : 4; }
+
+int32_t check_common(int64_t n, int32_t l_max, int32_t dtype) {
+  if (n < 0) return fail(SPH_ERR_INVALID, "n must be >= 0");
+  if (l_max < 0 || l_max > sph::kMaxLmax)
+    return fail(SPH_ERR_LMAX, "l_max must be in [0, " + std::to_string(sph::kMaxLmax) + "]");
+  if (dtype != SPH_F32 && dtype != SPH_F64) return fail(SPH_ERR_INVALID, "dtype must be SPH_F32 or SPH_F64");
+  return SPH_OK;
+}
+
+int32_t check_norm(int32_t normalize) {
+  if (normalize != 0 && normalize != 1) return fail(SPH_ERR_INVALID, "normalize must be 0 or 1");
+  return SPH_OK;
+}
+
+// Byte range [p, p+bytes) of a buffer, for overlap checks.
+struct Range {
+  const void* p;
+  size_t bytes;
+  const char* name;
+};
+
+int32_t check_no_overlap(std::initializer_list<Range> outs, std::initializer_list<Range> all) {
+  for (const Range& o : outs) {
+    if (o.p == nullptr || o.bytes == 0) continue;
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(o.p), a1 = a0 + o.bytes;
+    for (const Range& b : all) {
+      if (b.p == nullptr || b.bytes == 0 || b.p == o.p) continue;
+      const uintptr_t b0 = reinterpret_cast<uintptr_t>(b.p), b1 = b0 + b.bytes;
+      if (a0 < b1 && b0 < a1)
+        return fail(SPH_ERR_INVALID, std::string(o.name) + " overlaps " + b.name);
+    }
+  }
+  return SPH_OK;
+}
+
+sph::KernelInfo fwd_info(int32_t dtype, int L, int norm, int variant) {
+  return dtype == SPH_F64 ? sph::fwd_info_f64(L, norm, variant) : sph::fwd_info_f32(L, norm, variant);
+}
+sph::KernelInfo bwd_info(int32_t dtype, int L) {
+  return dtype == SPH_F64 ? sph::bwd_info_f64(L) : sph::bwd_info_f32(L);
+}
+sph::KernelInfo dbwd_info(int32_t dtype, int L, int norm) {
+  return dtype == SPH_F64 ? sph::dbwd_info_f64(L, norm) : sph::dbwd_info_f32(L, norm);
+}
+
+// Kernels whose dynamic LDS exceeds the default limit get the attribute once.
+std::mutex g_attr_mu;
+std::map<std::pair<int, const void*>, size_t> g_attr_set;
+
+hipError_t ensure_lds(const void* fn, size_t bytes) {
+  if (bytes <= 48 * 1024) return hipSuccess;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_attr_mu);
+  auto key = std::make_pair(dev, fn);
+  auto it = g_attr_set.find(key);
+  if (it != g_attr_set.end() && it->second >= bytes) return hipSuccess;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+  if (e == hipSuccess) g_attr_set[key] = bytes;
+  return e;
+}
+
+int num_cus() {
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+    return 256;
+  return n;
+}
+
+hipError_t launch(const void* fn, unsigned grid, unsigned block, size_t lds, void* params,
+                  hipStream_t s) {
+  void* args[] = {params};
+  hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, s);
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ------------------------------------------------------------ batched path
+struct BatchKey {
+  int dev, dtype, L, norm, store_dy, bwd;
+  bool operator<(const BatchKey& o) const {
+    return std::tie(dev, dtype, L, norm, store_dy, bwd) <
+           std::tie(o.dev, o.dtype, o.L, o.norm, o.store_dy, o.bwd);
+  }
+};
+
+struct Choice {
+  int variant = 0;
+  int blocks_per_cu = 8;
+};
+
+struct GraphEntry {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraphNode_t node = nullptr;
+  const void* fn = nullptr;
+  unsigned grid = 0;
+  size_t lds = 0;
+};
+
+std::mutex g_batch_mu;
+std::map<BatchKey, Choice> g_choice;
+std::map<std::tuple<BatchKey, const void*, unsigned, size_t>, GraphEntry> g_graphs;
+int g_use_graph = 1;
+int g_autotune = 1;
+bool g_cache_loaded = false;
+
+constexpr int kBpcCandidates[] = {2, 4, 8, 16};
+
+std::string cache_path() {
+  const char* p = std::getenv("SPH_AUTOTUNE_CACHE");
+  return p ? std::string(p) : std::string();
+}
+
+// Cache file: one line per combination,
+//   dtype L normalize store_dY backward variant blocks_per_cu
+// Unreadable or malformed lines are ignored (defaults apply).
+void load_cache_locked() {
+  if (g_cache_loaded) return;
+  g_cache_loaded = true;
+  const std::string path = cache_path();
+  if (path.empty()) return;
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    std::istringstream is(line);
+    int dt, L, nm, sd, bw, v, b;
+    if (!(is >> dt >> L >> nm >> sd >> bw >> v >> b)) continue;
+    if (dt < 0 || dt > 1 || L < 0 || L > sph::kMaxLmax || v < 0 || v >= sph::kNumBudgetVariants ||
+        b < 1 || b > 64)
+      continue;
+    for (int dev = 0; dev < 64; ++dev) g_choice[BatchKey{dev, dt, L, nm, sd, bw}] = Choice{v, b};
+  }
+}
+
+void save_cache_locked() {
+  const std::string path = cache_path();
+  if (path.empty()) return;
+  std::ofstream f(path, std::ios::trunc);
+  if (!f) return;
+  for (const auto& kv : g_choice) {
+    if (kv.first.dev != 0) continue;
+    f << kv.first.dtype << ' ' << kv.first.L << ' ' << kv.first.norm << ' ' << kv.first.store_dy << ' '
+      << kv.first.bwd << ' ' << kv.second.variant << ' ' << kv.second.blocks_per_cu << '\n';
+  }
+}
+
+size_t batched_lds(const sph::KernelInfo& ki, bool bwd) { return ki.tile_lds_bytes * (bwd ? 2 : 1); }
+
+// Times every (variant, blocks_per_cu) on the caller's buffers (the kernel
+// is a pure function of its inputs, so repeated runs leave the right
+// result) and returns the fastest.  Synchronises the host.
+Choice autotune(int32_t dtype, int L, int norm, sph::FwdParams params, bool bwd, hipStream_t s) {
+  Choice best;
+  float best_ms = 1e30f;
+  const int cus = num_cus();
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return best;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return best;
+  }
+  const int64_t tiles = ceil_div(params.n, sph::kPointsPerBlock);
+  for (int v = 0; v < sph::kNumBudgetVariants; ++v) {
+    const sph::KernelInfo ki = fwd_info(dtype, L, norm, v);
+    const size_t lds = batched_lds(ki, bwd);
+    if (ki.fn == nullptr || ensure_lds(ki.fn, lds) != hipSuccess) continue;
+    for (int bpc : kBpcCandidates) {
+      const unsigned grid = static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(tiles, int64_t(cus) * bpc)));
+      sph::FwdParams p = params;
+      if (launch(ki.fn, grid, sph::kBlock, lds, &p, s) != hipSuccess) continue;  // warm-up
+      (void)hipEventRecord(e0, s);
+      constexpr int reps = 3;
+      bool okr = true;
+      for (int r = 0; r < reps && okr; ++r) okr = launch(ki.fn, grid, sph::kBlock, lds, &p, s) == hipSuccess;
+      (void)hipEventRecord(e1, s);
+      if (!okr || hipEventSynchronize(e1) != hipSuccess) continue;
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) continue;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = Choice{v, bpc};
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipGetLastError();
+  return best;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t sph_num_components(int32_t l_max) { return l_max < 0 ? -1 : (l_max + 1) * (l_max + 1); }
+
+int32_t sph_max_lmax(void) { return sph::kMaxLmax; }
+
+const char* sph_status_string(int32_t status) {
+  switch (status) {
+    case SPH_OK: return "success";
+    case SPH_ERR_NULL: return "a required pointer is NULL";
+    case SPH_ERR_INVALID: return "invalid argument";
+    case SPH_ERR_LMAX: return "l_max out of range";
+    case SPH_ERR_OFFSETS: return "inconsistent CSR offsets";
+    case SPH_ERR_DEVICE: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+const char* sph_last_error(void) { return g_last_error.c_str(); }
+
+const char* sph_version(void) { return "1.0.0 gfx950"; }
+
+int32_t sph_compute_with_gradients(const void* xyz, int64_t n, int32_t l_max, int32_t normalize,
+                                   int32_t dtype, void* Y, void* dY, void* stream) {
+  int32_t st = check_common(n, l_max, dtype);
+  if (st != SPH_OK) return st;
+  if ((st = check_norm(normalize)) != SPH_OK) return st;
+  if (n == 0) return ok();
+  if (xyz == nullptr || Y == nullptr) return fail(SPH_ERR_NULL, "xyz and Y are required");
+  const size_t w = elem_size(dtype);
+  const size_t K = static_cast<size_t>(sph_num_components(l_max));
+  const size_t un = static_cast<size_t>(n);
+  if ((st = check_no_overlap({{Y, un * K * w, "Y"}, {dY, un * 3 * K * w, "dY"}},
+                             {{xyz, un * 3 * w, "xyz"}, {Y, un * K * w, "Y"}, {dY, un * 3 * K * w, "dY"}})) !=
+      SPH_OK)
+    return st;
+  const sph::KernelInfo ki = fwd_info(dtype, l_max, normalize, 0);
+  if (ki.fn == nullptr) return fail(SPH_ERR_INVALID, "no kernel for these arguments");
+  hipError_t e = ensure_lds(ki.fn, ki.tile_lds_bytes);
+  if (e != hipSuccess) return device_fail(e, "hipFuncSetAttribute");
+  sph::FwdParams p{xyz, n, l_max, Y, dY, nullptr, nullptr, nullptr, 0, nullptr};
+  const int64_t grid = ceil_div(n, sph::kPointsPerBlock);
+  if (grid > 0x7fffffff) return fail(SPH_ERR_INVALID, "n too large for one launch");
+  e = launch(ki.fn, static_cast<unsigned>(grid), sph::kBlock, ki.tile_lds_bytes, &p,
+             static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_fail(e, "forward launch");
+  return ok();
+}
+
+int32_t sph_compute(const void* xyz, int64_t n, int32_t l_max, int32_t normalize, int32_t dtype, void* Y,
+                    void* stream) {
+  return sph_compute_with_gradients(xyz, n, l_max, normalize, dtype, Y, nullptr, stream);
+}
+
+int32_t sph_backward(const void* dY, const void* grad_Y, int64_t n, int32_t l_max, int32_t dtype,
+                     void* grad_xyz, void* stream) {
+  int32_t st = check_common(n, l_max, dtype);
+  if (st != SPH_OK) return st;
+  if (n == 0) return ok();
+  if (dY == nullptr || grad_Y == nullptr || grad_xyz == nullptr)
+    return fail(SPH_ERR_NULL, "dY, grad_Y and grad_xyz are required");
+  const size_t w = elem_size(dtype);
+  const size_t K = static_cast<size_t>(sph_num_components(l_max));
+  const size_t un = static_cast<size_t>(n);
+  if ((st = check_no_overlap({{grad_xyz, un * 3 * w, "grad_xyz"}},
+                             {{dY, un * 3 * K * w, "dY"}, {grad_Y, un * K * w, "grad_Y"}})) != SPH_OK)
+    return st;
+  const sph::KernelInfo ki = bwd_info(dtype, l_max);
+  if (ki.fn == nullptr) return fail(SPH_ERR_INVALID, "no kernel for these arguments");
+  sph::BwdParams p{dY, grad_Y, n, static_cast<int32_t>(K), grad_xyz};
+  const int64_t grid = ceil_div(n, sph::kBwdPointsPerBlock);
+  if (grid > 0x7fffffff) return fail(SPH_ERR_INVALID, "n too large for one launch");
+  hipError_t e = launch(ki.fn, static_cast<unsigned>(grid), sph::kBlock, 0, &p, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_fail(e, "backward launch");
+  return ok();
+}
+
+int32_t sph_double_backward(const void* xyz, const void* grad_Y, const void* v, int64_t n, int32_t l_max,
+                            int32_t normalize, int32_t dtype, void* grad_grad_Y, void* grad_xyz2,
+                            void* stream) {
+  int32_t st = check_common(n, l_max, dtype);
+  if (st != SPH_OK) return st;
+  if ((st = check_norm(normalize)) != SPH_OK) return st;
+  if (n == 0 || (grad_grad_Y == nullptr && grad_xyz2 == nullptr)) return ok();
+  if (xyz == nullptr || grad_Y == nullptr || v == nullptr)
+    return fail(SPH_ERR_NULL, "xyz, grad_Y and v are required");
+  const size_t w = elem_size(dtype);
+  const size_t K = static_cast<size_t>(sph_num_components(l_max));
+  const size_t un = static_cast<size_t>(n);
+  if ((st = check_no_overlap(
+           {{grad_grad_Y, un * K * w, "grad_grad_Y"}, {grad_xyz2, un * 3 * w, "grad_xyz2"}},
+           {{xyz, un * 3 * w, "xyz"}, {grad_Y, un * K * w, "grad_Y"}, {v, un * 3 * w, "v"},
+            {grad_grad_Y, un * K * w, "grad_grad_Y"}, {grad_xyz2, un * 3 * w, "grad_xyz2"}})) != SPH_OK)
+    return st;
+  const sph::KernelInfo ki = dbwd_info(dtype, l_max, normalize);
+  if (ki.fn == nullptr) return fail(SPH_ERR_INVALID, "no kernel for these arguments");
+  hipError_t e = ensure_lds(ki.fn, ki.tile_lds_bytes);
+  if (e != hipSuccess) return device_fail(e, "hipFuncSetAttribute");
+  sph::DbwdParams p{xyz, grad_Y, v, n, l_max, grad_grad_Y, grad_xyz2};
+  const int64_t grid = ceil_div(n, sph::kPointsPerBlock);
+  if (grid > 0x7fffffff) return fail(SPH_ERR_INVALID, "n too large for one launch");
+  e = launch(ki.fn, static_cast<unsigned>(grid), sph::kBlock, ki.tile_lds_bytes, &p,
+             static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_fail(e, "double backward launch");
+  return ok();
+}
+
+int32_t sph_batched_set_options(int32_t use_graph, int32_t autotune) {
+  if ((use_graph != 0 && use_graph != 1) || (autotune != 0 && autotune != 1))
+    return fail(SPH_ERR_INVALID, "options must be 0 or 1");
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  g_use_graph = use_graph;
+  g_autotune = autotune;
+  return ok();
+}
+
+int32_t sph_batched_get_config(int32_t l_max, int32_t normalize, int32_t dtype, int32_t store_dY,
+                               int32_t with_backward, char* buf, int32_t len) {
+  if (buf == nullptr || len <= 0) return fail(SPH_ERR_NULL, "buf is required");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  auto it = g_choice.find(BatchKey{dev, dtype, l_max, normalize, store_dY ? 1 : 0, with_backward ? 1 : 0});
+  if (it == g_choice.end()) return fail(SPH_ERR_INVALID, "no configuration chosen yet");
+  const sph::KernelInfo ki = fwd_info(dtype, l_max, normalize, it->second.variant);
+  std::snprintf(buf, static_cast<size_t>(len), "variant=%d blocks_per_cu=%d budget=%d", it->second.variant,
+                it->second.blocks_per_cu, ki.budget);
+  return ok();
+}
+
+int32_t sph_batched_compute(const void* xyz, const int64_t* offsets, int64_t n_env, int64_t n_points,
+                            int32_t l_max, int32_t normalize, int32_t dtype, void* Y, void* dY,
+                            const void* grad_Y, void* grad_xyz, int32_t* status, void* stream) {
+  int32_t st = check_common(n_points, l_max, dtype);
+  if (st != SPH_OK) return st;
+  if ((st = check_norm(normalize)) != SPH_OK) return st;
+  if (n_env < 0) return fail(SPH_ERR_INVALID, "n_env must be >= 0");
+  if (offsets == nullptr) return fail(SPH_ERR_NULL, "offsets is required");
+  if (grad_Y != nullptr && grad_xyz == nullptr) return fail(SPH_ERR_NULL, "grad_xyz is required with grad_Y");
+  if (grad_Y == nullptr && grad_xyz != nullptr) return fail(SPH_ERR_INVALID, "grad_xyz given without grad_Y");
+  if (n_points > 0 && (xyz == nullptr || Y == nullptr)) return fail(SPH_ERR_NULL, "xyz and Y are required");
+  if (n_points == 0 && status == nullptr) return ok();
+  const size_t w = elem_size(dtype);
+  const size_t K = static_cast<size_t>(sph_num_components(l_max));
+  const size_t un = static_cast<size_t>(n_points);
+  if ((st = check_no_overlap({{Y, un * K * w, "Y"}, {dY, un * 3 * K * w, "dY"}, {grad_xyz, un * 3 * w, "grad_xyz"},
+                              {status, 4, "status"}},
+                             {{xyz, un * 3 * w, "xyz"}, {offsets, (static_cast<size_t>(n_env) + 1) * 8, "offsets"},
+                              {Y, un * K * w, "Y"}, {dY, un * 3 * K * w, "dY"}, {grad_Y, un * K * w, "grad_Y"},
+                              {grad_xyz, un * 3 * w, "grad_xyz"}, {status, 4, "status"}})) != SPH_OK)
+    return st;
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return device_fail(e, "hipGetDevice");
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  e = hipStreamIsCapturing(s, &cap);
+  if (e != hipSuccess) return device_fail(e, "hipStreamIsCapturing");
+  const bool capturing = cap != hipStreamCaptureStatusNone;
+
+  const bool bwd = grad_Y != nullptr;
+  const BatchKey key{dev, dtype, l_max, normalize, dY != nullptr ? 1 : 0, bwd ? 1 : 0};
+  sph::FwdParams p{xyz, n_points, l_max, Y, dY, grad_Y, grad_xyz, offsets, n_env, status};
+
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  load_cache_locked();
+  Choice ch;
+  auto it = g_choice.find(key);
+  if (it != g_choice.end()) {
+    ch = it->second;
+  } else if (g_autotune && !capturing && n_points >= int64_t(64) * 256) {
+    ch = autotune(dtype, l_max, normalize, p, bwd, s);
+    g_choice[key] = ch;
+    save_cache_locked();
+  } else {
+    g_choice[key] = ch;
+  }
+
+  const sph::KernelInfo ki = fwd_info(dtype, l_max, normalize, ch.variant);
+  if (ki.fn == nullptr) return fail(SPH_ERR_INVALID, "no kernel for these arguments");
+  const size_t lds = batched_lds(ki, bwd);
+  e = ensure_lds(ki.fn, lds);
+  if (e != hipSuccess) return device_fail(e, "hipFuncSetAttribute");
+  const int64_t tiles = ceil_div(n_points, sph::kPointsPerBlock);
+  const unsigned grid = static_cast<unsigned>(
+      std::max<int64_t>(1, std::min<int64_t>(tiles, int64_t(num_cus()) * ch.blocks_per_cu)));
+
+  if (!g_use_graph || capturing) {
+    e = launch(ki.fn, grid, sph::kBlock, lds, &p, s);
+    if (e != hipSuccess) return device_fail(e, "batched launch");
+    return ok();
+  }
+
+  // One graph per (combination, kernel, grid, LDS); later calls update the
+  // kernel node's arguments and replay it.
+  auto gkey = std::make_tuple(key, ki.fn, grid, lds);
+  GraphEntry& g = g_graphs[gkey];
+  void* args[] = {&p};
+  hipKernelNodeParams np{};
+  np.blockDim = dim3(sph::kBlock);
+  np.gridDim = dim3(grid);
+  np.func = const_cast<void*>(ki.fn);
+  np.kernelParams = args;
+  np.sharedMemBytes = static_cast<unsigned>(lds);
+  np.extra = nullptr;
+  if (g.exec == nullptr) {
+    if ((e = hipGraphCreate(&g.graph, 0)) != hipSuccess) return device_fail(e, "hipGraphCreate");
+    if ((e = hipGraphAddKernelNode(&g.node, g.graph, nullptr, 0, &np)) != hipSuccess) {
+      (void)hipGraphDestroy(g.graph);
+      g = GraphEntry{};
+      return device_fail(e, "hipGraphAddKernelNode");
+    }
+    if ((e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0)) != hipSuccess) {
+      (void)hipGraphDestroy(g.graph);
+      g = GraphEntry{};
+      return device_fail(e, "hipGraphInstantiate");
+    }
+    g.fn = ki.fn;
+    g.grid = grid;
+    g.lds = lds;
+  } else {
+    if ((e = hipGraphExecKernelNodeSetParams(g.exec, g.node, &np)) != hipSuccess)
+      return device_fail(e, "hipGraphExecKernelNodeSetParams");
+  }
+  if ((e = hipGraphLaunch(g.exec, s)) != hipSuccess) return device_fail(e, "hipGraphLaunch");
+  return ok();
+}
+
+}  // extern "C"

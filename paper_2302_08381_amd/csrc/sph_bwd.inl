@@ -1,0 +1,72 @@
+// Backward (vector-Jacobian product) with stored derivatives:
+//   gxyz[i,a] = sum_k gY[i,k] dY[i,a,k]
+// A streaming contraction (no MFMA: one short dot product per point and
+// axis).  A block of 64 lanes takes 16 points; the gY rows and the 48 dY rows
+// of those points are copied into LDS with coalesced (16-byte when possible)
+// loads, in chunks of at most KC columns.  Lane (p, q) then sums columns
+// k = q (mod 4) of point p for the three axes, and the four partial sums are
+// combined with two lane exchanges.  The summation order is fixed, so the
+// result is deterministic.
+#pragma once
+
+#include "sph_device.hpp"
+#include "sph_launch.hpp"
+
+namespace sph {
+
+template <typename T>
+inline constexpr int kBwdChunk = 84;
+template <>
+inline constexpr int kBwdChunk<double> = 42;
+
+template <typename T>
+__global__ __launch_bounds__(kWave) void k_bwd(BwdParams P) {
+  constexpr int PP = kBwdPointsPerBlock;  // 16 points per block
+  constexpr int KC = kBwdChunk<T>;
+  constexpr int SC = KC | 1;
+  __shared__ __align__(16) T sg[PP * SC];
+  __shared__ __align__(16) T sd[3 * PP * SC];
+  const int K = P.K;
+  const int lane = threadIdx.x;
+  const int pl = lane >> 2;
+  const int q = lane & 3;
+  const int64_t p0 = static_cast<int64_t>(blockIdx.x) * PP;
+  if (p0 >= P.n) return;
+  const int np = static_cast<int>(P.n - p0 < PP ? P.n - p0 : PP);
+  const T* gY = static_cast<const T*>(P.gY) + p0 * K;
+  const T* dY = static_cast<const T*>(P.dY) + p0 * 3 * K;
+
+  T a0 = T(0), a1 = T(0), a2 = T(0);
+  for (int kc0 = 0; kc0 < K; kc0 += KC) {
+    const int cnt = (K - kc0) < KC ? (K - kc0) : KC;
+    const int S = cnt | 1;
+    copy_in(sg, S, gY + kc0, K, cnt, np, lane, aligned16(gY + kc0));
+    copy_in(sd, S, dY + kc0, K, cnt, 3 * np, lane, aligned16(dY + kc0));
+    __syncthreads();
+    if (pl < np) {
+      const T* g = sg + pl * S;
+      const T* d0 = sd + (3 * pl) * S;
+      const T* d1 = d0 + S;
+      const T* d2 = d1 + S;
+      for (int k = q; k < cnt; k += 4) {
+        const T gv = g[k];
+        a0 += gv * d0[k];
+        a1 += gv * d1[k];
+        a2 += gv * d2[k];
+      }
+    }
+    __syncthreads();
+  }
+  a0 += __shfl_xor(a0, 1);
+  a1 += __shfl_xor(a1, 1);
+  a2 += __shfl_xor(a2, 1);
+  a0 += __shfl_xor(a0, 2);
+  a1 += __shfl_xor(a1, 2);
+  a2 += __shfl_xor(a2, 2);
+  if (pl < np && q < 3) {
+    const T v = (q == 0) ? a0 : (q == 1 ? a1 : a2);
+    static_cast<T*>(P.gxyz)[(p0 + pl) * 3 + q] = v;
+  }
+}
+
+}  // namespace sph

@@ -1,0 +1,320 @@
+// Device building blocks shared by the libsph kernels (gfx950, wave64).
+//
+// One lane owns one point.  For every degree l the lane builds the row
+// Qt_l^0..Qt_l^l from scratch by the folded downward-in-m recursion (rows are
+// independent of each other, Eq. iter-q-alt), and s_m, c_m by Eq. iter-sc
+// while walking m upward.  A row together with the previous one (and the one
+// before, for second derivatives) gives every value and derivative of degree
+// l (Eqs. real-sh-cartesian and iter-deri).
+//
+// Output staging: values of one component (Y, d/dx, d/dy or d/dz) for a
+// group of consecutive degrees are written by each lane into its own row of
+// an LDS tile ([64 points][stride]); the wave then copies the tile out so
+// that consecutive lanes write consecutive addresses of the point-major
+// global arrays.  An odd LDS stride keeps the per-lane writes free of bank
+// conflicts.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "sph_coeffs.hpp"
+
+namespace sph {
+
+constexpr int kWave = 64;
+
+constexpr CoefTable<float> kCoefF = make_coef_table<float>();
+constexpr CoefTable<double> kCoefD = make_coef_table<double>();
+
+template <typename T>
+__device__ __forceinline__ constexpr const CoefTable<T>& coef();
+template <>
+__device__ __forceinline__ constexpr const CoefTable<float>& coef<float>() { return kCoefF; }
+template <>
+__device__ __forceinline__ constexpr const CoefTable<double>& coef<double>() { return kCoefD; }
+
+// 16-byte native vectors (clang ext_vector_type, usable with the
+// nontemporal builtins).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  using type = f32x4;
+  static constexpr int n = 4;
+};
+template <>
+struct Vec16<double> {
+  using type = f64x2;
+  static constexpr int n = 2;
+};
+
+// ------------------------------------------------------------ group plans
+// Consecutive degrees are grouped so that one component of one group fits
+// the per-point LDS budget (in elements).  A single degree larger than the
+// budget forms a group of its own.
+struct Plan {
+  int ng;
+  int lo[kMaxL + 1];  // first degree of group g
+  int hi[kMaxL + 1];  // one past the last degree
+  int stride;         // LDS elements per point (odd)
+};
+
+__host__ __device__ constexpr Plan make_plan(int L, int budget) {
+  Plan p{};
+  p.ng = 0;
+  int mx = 1;
+  int la = 0;
+  while (la <= L) {
+    int lb = la + 1;
+    while (lb <= L && (lb + 1) * (lb + 1) - la * la <= budget) ++lb;
+    p.lo[p.ng] = la;
+    p.hi[p.ng] = lb;
+    ++p.ng;
+    const int cnt = lb * lb - la * la;
+    if (cnt > mx) mx = cnt;
+    la = lb;
+  }
+  p.stride = (mx % 2 == 0) ? mx + 1 : mx;
+  return p;
+}
+
+// LDS stride (elements per point) of the largest group for l_max = L; the
+// same value as make_plan(L, budget).stride without the per-group arrays.
+__host__ __device__ constexpr int plan_stride(int L, int budget) {
+  int mx = 1;
+  for (int la = 0; la <= L;) {
+    int lb = la + 1;
+    while (lb <= L && (lb + 1) * (lb + 1) - la * la <= budget) ++lb;
+    const int cnt = lb * lb - la * la;
+    if (cnt > mx) mx = cnt;
+    la = lb;
+  }
+  return (mx % 2 == 0) ? mx + 1 : mx;
+}
+
+// End (exclusive) of the group of degrees starting at la.
+__host__ __device__ constexpr int group_end(int la, int L, int budget) {
+  int lb = la + 1;
+  while (lb <= L && (lb + 1) * (lb + 1) - la * la <= budget) ++lb;
+  return lb;
+}
+
+// m-extent buckets: a kernel instantiated for MM serves every l_max <= MM
+// (its m loops are unrolled to MM and exit at the row's degree).
+constexpr int kNumBuckets = 8;
+constexpr int kBuckets[kNumBuckets] = {2, 4, 6, 8, 12, 16, 24, 32};
+__host__ __device__ constexpr int bucket_index(int L) {
+  for (int i = 0; i < kNumBuckets; ++i)
+    if (L <= kBuckets[i]) return i;
+  return -1;
+}
+
+// ------------------------------------------------------------ recursions
+// Row l of the folded polynomials: q[m] = Qt_l^m for 0 <= m <= l (l <= MM).
+// Entries m > l are left untouched: no caller reads them (every read of a
+// neighbouring row is guarded by the degree conditions of its formula).
+// l < 0 writes nothing.
+template <typename T, int MM>
+__device__ __forceinline__ void q_row(int l, T z, T rxy2, T (&q)[MM + 3]) {
+  const CoefTable<T>& C = coef<T>();
+#pragma unroll
+  for (int m = MM; m >= 0; --m) {
+    if (m > l) continue;
+    if (m == l) {
+      q[m] = C.qll[l];
+    } else if (m == l - 1) {
+      q[m] = (C.b1[l][m] * z) * q[m + 1];
+    } else {
+      q[m] = (C.b1[l][m] * z) * q[m + 1] + (C.b2[l][m] * rxy2) * q[m + 2];
+    }
+  }
+}
+
+// dst[m] = src[m] for m <= l.
+template <typename T, int MM>
+__device__ __forceinline__ void copy_row(int l, const T (&src)[MM + 3], T (&dst)[MM + 3]) {
+#pragma unroll
+  for (int m = 0; m <= MM; ++m) {
+    if (m > l) break;
+    dst[m] = src[m];
+  }
+}
+
+// Component ids of a pass: 0 = value, 1..3 = d/dx, d/dy, d/dz.
+// emit_row calls sink(k, value) for every column k = l^2 + l + m of degree l.
+//   (ex, ey, ez): evaluation point (x/r for the normalised harmonics)
+//   inv_r:        1/r (normalised only; 0 at the origin)
+// Scaled derivatives (Eq. iter-deri and the product rule), with
+// Tm = gxy * Qt_{l-1}^{m+1}, Cm = gz * Qt_{l-1}^m:
+//   d/dx: x Tm {c_m, s_m} + m Qt_l^m {c_{m-1}, s_{m-1}}
+//   d/dy: y Tm {c_m, s_m} + m Qt_l^m {-s_{m-1}, c_{m-1}}
+//   d/dz: Cm {c_m, s_m}
+// Normalised (chain rule through u = x/r): (d_a(u) - l u_a Y(u)) / r.
+template <typename T, int MM, int COMP, bool NORM, typename Sink>
+__device__ __forceinline__ void emit_row(int l, const T (&prev)[MM + 3], const T (&cur)[MM + 3],
+                                         T ex, T ey, T ez, T inv_r, Sink&& sink) {
+  const CoefTable<T>& C = coef<T>();
+  constexpr T kIS2 = T(kInvSqrt2d);
+  const int k0 = l * l + l;
+  T lu = T(0);
+  if constexpr (NORM && COMP != 0) lu = T(l) * (COMP == 1 ? ex : (COMP == 2 ? ey : ez));
+  T sp = T(0), cp = T(1);  // s_{m-1}, c_{m-1}
+  T s = T(0), c = T(1);    // s_m, c_m
+#pragma unroll
+  for (int m = 0; m <= MM; ++m) {
+    if (m > l) break;
+    if (m > 0) {
+      const T sn = ex * s + ey * c;
+      const T cn = ex * c - ey * s;
+      sp = s;
+      cp = c;
+      s = sn;
+      c = cn;
+    }
+    const T q = cur[m];
+    if constexpr (COMP == 0) {
+      if (m == 0) {
+        sink(k0, q * kIS2);
+      } else {
+        sink(k0 + m, q * c);
+        sink(k0 - m, q * s);
+      }
+    } else {
+      T Tm = T(0), Cm = T(0);
+      if (COMP != 3 && m <= l - 2) Tm = C.gxy[l][m] * prev[m + 1];
+      if (COMP == 3 && m <= l - 1) Cm = C.gz[l][m] * prev[m];
+      if (m == 0) {
+        T d = (COMP == 1) ? ex * Tm : (COMP == 2 ? ey * Tm : Cm);
+        d *= kIS2;
+        if constexpr (NORM) d = (d - lu * (q * kIS2)) * inv_r;
+        sink(k0, d);
+      } else {
+        const T mq = T(m) * q;
+        T dp, dm;
+        if constexpr (COMP == 1) {
+          const T xt = ex * Tm;
+          dp = xt * c + mq * cp;
+          dm = xt * s + mq * sp;
+        } else if constexpr (COMP == 2) {
+          const T yt = ey * Tm;
+          dp = yt * c - mq * sp;
+          dm = yt * s + mq * cp;
+        } else {
+          dp = Cm * c;
+          dm = Cm * s;
+        }
+        if constexpr (NORM) {
+          dp = (dp - lu * (q * c)) * inv_r;
+          dm = (dm - lu * (q * s)) * inv_r;
+        }
+        sink(k0 + m, dp);
+        sink(k0 - m, dm);
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------ evaluation point
+template <typename T>
+struct Point {
+  T ex, ey, ez;  // evaluation point
+  T rxy2;        // ex^2 + ey^2
+  T inv_r;       // normalised only
+};
+
+template <typename T, bool NORM>
+__device__ __forceinline__ Point<T> make_point(T x, T y, T z) {
+  Point<T> p;
+  if constexpr (NORM) {
+    const T r = sqrt(x * x + y * y + z * z);
+    // r == 0 -> inv_r = 0: every l >= 1 value and every derivative vanishes,
+    // Y_0^0 keeps its constant.  NaN stays NaN.
+    const T ir = (r == T(0)) ? T(0) : T(1) / r;
+    p.ex = x * ir;
+    p.ey = y * ir;
+    p.ez = z * ir;
+    p.inv_r = ir;
+  } else {
+    p.ex = x;
+    p.ey = y;
+    p.ez = z;
+    p.inv_r = T(0);
+  }
+  p.rxy2 = p.ex * p.ex + p.ey * p.ey;
+  return p;
+}
+
+// ------------------------------------------------------------ LDS <-> global
+// Copy a staged tile out: for point p < np and j < cnt,
+//   dst[p * gstride + j] = st[p * S + j].
+// With gstride == cnt == S (one contiguous block) and 16-byte aligned dst the
+// copy uses 16-byte vector accesses.
+template <typename T>
+__device__ __forceinline__ void copy_out(const T* __restrict__ st, int S, T* __restrict__ dst,
+                                         int gstride, int cnt, int np, int lane, bool vec) {
+  const int total = np * cnt;
+  if (vec && gstride == cnt && S == cnt) {
+    using V = typename Vec16<T>::type;
+    constexpr int W = Vec16<T>::n;
+    const int nv = total / W;
+    const V* sv = reinterpret_cast<const V*>(st);
+    V* dv = reinterpret_cast<V*>(dst);
+    for (int i = lane; i < nv; i += kWave) __builtin_nontemporal_store(sv[i], dv + i);
+    for (int j = nv * W + lane; j < total; j += kWave) __builtin_nontemporal_store(st[j], dst + j);
+    return;
+  }
+  int p = lane / cnt;
+  int k = lane - p * cnt;
+  const int qs = kWave / cnt;
+  const int rs = kWave - qs * cnt;
+  for (int j = lane; j < total; j += kWave) {
+    __builtin_nontemporal_store(st[p * S + k], dst + (p * gstride + k));
+    p += qs;
+    k += rs;
+    if (k >= cnt) {
+      k -= cnt;
+      ++p;
+    }
+  }
+}
+
+// The reverse: st[p * S + j] = src[p * gstride + j].
+template <typename T>
+__device__ __forceinline__ void copy_in(T* __restrict__ st, int S, const T* __restrict__ src,
+                                        int gstride, int cnt, int np, int lane, bool vec) {
+  const int total = np * cnt;
+  if (vec && gstride == cnt && S == cnt) {
+    using V = typename Vec16<T>::type;
+    constexpr int W = Vec16<T>::n;
+    const int nv = total / W;
+    V* sv = reinterpret_cast<V*>(st);
+    const V* dv = reinterpret_cast<const V*>(src);
+    for (int i = lane; i < nv; i += kWave) sv[i] = __builtin_nontemporal_load(dv + i);
+    for (int j = nv * W + lane; j < total; j += kWave) st[j] = __builtin_nontemporal_load(src + j);
+    return;
+  }
+  int p = lane / cnt;
+  int k = lane - p * cnt;
+  const int qs = kWave / cnt;
+  const int rs = kWave - qs * cnt;
+  for (int j = lane; j < total; j += kWave) {
+    st[p * S + k] = __builtin_nontemporal_load(src + (p * gstride + k));
+    p += qs;
+    k += rs;
+    if (k >= cnt) {
+      k -= cnt;
+      ++p;
+    }
+  }
+}
+
+__device__ __forceinline__ bool aligned16(const void* p) {
+  return (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
+}
+
+}  // namespace sph

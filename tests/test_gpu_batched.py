@@ -1,0 +1,143 @@
+"""Batched CSR entry point (sph_batched_compute): one persistent launch over
+many neighbour lists, replayed from cached hipGraphs, with the backward
+fused in."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from workloads import SEEDS, csr_environments, standard_normal
+
+from _gpu_common import TOL, host_points, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _offsets(o):
+    return torch.as_tensor(o, dtype=torch.int64, device="cuda")
+
+
+@pytest.mark.parametrize("l_max", [3, 6, 8, 12, 20])
+def test_batched_equals_plain_and_oracle(l_max):
+    import paper_2302_08381_amd as sph
+    pts, offs = csr_environments(400, 8, 128, 0.5, 5.0, 60 + l_max)
+    n = int(offs[-1])
+    K = (l_max + 1) ** 2
+    xyz = to_dev(pts, torch.float32)
+    gY = to_dev(standard_normal((n, K), 70 + l_max), torch.float32)
+    status = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    out = sph.sph_batched_compute(xyz, _offsets(offs), l_max, True, store_dY=True, grad_Y=gY, status=status)
+    Y, dY = sph.sph_compute_with_gradients(xyz, l_max, True)
+    gx = sph.sph_backward(dY, gY, l_max)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    # same device function on the same point: bitwise equal values
+    assert torch.equal(out["Y"], Y)
+    assert torch.equal(out["dY"], dY)
+    # fused backward sums in another order
+    scale = (gY.abs().double()[:, None, :] * dY.abs().double()).sum(2) + 1e-30
+    rel = ((out["grad_xyz"].double() - gx.double()).abs() / scale).max()
+    assert float(rel) < 1e-5
+    # and against the oracle on a sample
+    idx = torch.arange(0, n, 37, device="cuda")
+    hp = host_points(xyz[idx])
+    Yr, Gr = oracle.real_sph(hp, l_max, True)
+    gYh = gY[idx].double().cpu().numpy()
+    ref = oracle.backward(Gr, gYh)
+    _, g, _ = oracle.component_scales(hp, l_max, True)
+    s = (np.abs(gYh) * g).sum(1)[:, None]
+    err = np.abs(out["grad_xyz"][idx].cpu().numpy() - np.asarray(ref, float)) / s
+    assert err.max() <= TOL[torch.float32]
+
+
+def test_batched_output_variants_and_graph_replay():
+    import paper_2302_08381_amd as sph
+    L = 6
+    K = 49
+    for rep in range(4):
+        pts, offs = csr_environments(100 + 7 * rep, 8, 128, 0.5, 5.0, 80 + rep)
+        n = int(offs[-1])
+        xyz = to_dev(pts, torch.float64)
+        gY = to_dev(standard_normal((n, K), 90 + rep), torch.float64)
+        Y, dY = sph.sph_compute_with_gradients(xyz, L, True)
+        gx = sph.sph_backward(dY, gY, L)
+        a = sph.sph_batched_compute(xyz, _offsets(offs), L, True, store_dY=False)
+        b = sph.sph_batched_compute(xyz, _offsets(offs), L, True, store_dY=False, grad_Y=gY)
+        c = sph.sph_batched_compute(xyz, _offsets(offs), L, True, store_dY=True)
+        torch.cuda.synchronize()
+        assert a["dY"] is None and a["grad_xyz"] is None and torch.equal(a["Y"], Y)
+        assert b["dY"] is None and torch.equal(b["Y"], Y)
+        assert float(((b["grad_xyz"] - gx).abs()).max()) < 1e-12 * float(gx.abs().max() + 1)
+        assert torch.equal(c["Y"], Y) and torch.equal(c["dY"], dY)
+
+
+def test_batched_without_graph_matches():
+    import paper_2302_08381_amd as sph
+    pts, offs = csr_environments(200, 8, 128, 0.5, 5.0, 99)
+    xyz = to_dev(pts, torch.float32)
+    a = sph.sph_batched_compute(xyz, _offsets(offs), 8, True)
+    sph.sph_batched_set_options(use_graph=False, autotune=True)
+    try:
+        b = sph.sph_batched_compute(xyz, _offsets(offs), 8, True)
+    finally:
+        sph.sph_batched_set_options(use_graph=True, autotune=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a["Y"], b["Y"]) and torch.equal(a["dY"], b["dY"])
+
+
+def test_batched_empty_environments_and_status():
+    import paper_2302_08381_amd as sph
+    rng = np.random.default_rng(5)
+    counts = rng.integers(0, 5, 300)  # many empty environments
+    counts[:10] = 0
+    offs = np.zeros(301, np.int64)
+    np.cumsum(counts, out=offs[1:])
+    n = int(offs[-1])
+    pts = rng.standard_normal((n, 3))
+    xyz = to_dev(pts, torch.float32)
+    st = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    out = sph.sph_batched_compute(xyz, _offsets(offs), 3, False, status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    assert torch.equal(out["Y"], sph.sph_compute(xyz, 3, False))
+    # inconsistent offsets: decreasing, wrong start, wrong end
+    for bad in (np.array([0, 5, 3, n]), np.array([1, 2, 3, n]), np.array([0, 1, 2, n + 1])):
+        st.fill_(-1)
+        sph.sph_batched_compute(xyz, _offsets(bad), 3, False, status=st)
+        torch.cuda.synchronize()
+        assert int(st.item()) == 4
+    # zero points, zero environments: the status is still written
+    st.fill_(-1)
+    e = torch.empty((0, 3), dtype=torch.float32, device="cuda")
+    sph.sph_batched_compute(e, _offsets(np.zeros(1, np.int64)), 3, False, status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+
+
+def test_batched_workload_autotuned_per_lmax():
+    """20 000 environments (8..128 neighbours, shell 0.5..5), float32,
+    normalised, a sequence of calls with l_max drawn from {3, 6, 8, 12}."""
+    import paper_2302_08381_amd as sph
+    pts, offs = csr_environments(20_000, 8, 128, 0.5, 5.0, SEEDS["batched"])
+    n = int(offs[-1])
+    xyz = to_dev(pts, torch.float32)
+    o = _offsets(offs)
+    rng = np.random.default_rng(SEEDS["batched"])
+    seq = rng.choice([3, 6, 8, 12], 16)
+    st = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    for L in seq:
+        L = int(L)
+        K = (L + 1) ** 2
+        gY = to_dev(standard_normal((n, K), 1000 + L), torch.float32)
+        out = sph.sph_batched_compute(xyz, o, L, True, store_dY=True, grad_Y=gY, status=st)
+        torch.cuda.synchronize()
+        assert int(st.item()) == 0
+        cfg = sph.sph_batched_get_config(L, True, torch.float32, True, True)
+        assert cfg is not None and "variant=" in cfg
+        idx = torch.arange(0, n, 1999, device="cuda")
+        hp = host_points(xyz[idx])
+        Yr, Gr = oracle.real_sph(hp, L, True)
+        mx, _ = oracle.per_l_errors(out["Y"][idx].cpu().numpy(), Yr, hp, L, True, "Y")
+        assert mx.max() <= TOL[torch.float32]
+        mx, _ = oracle.per_l_errors(out["dY"][idx].cpu().numpy(), Gr, hp, L, True, "dY")
+        assert mx.max() <= TOL[torch.float32]

@@ -1,0 +1,149 @@
+"""Forward kernels (sph_compute, sph_compute_with_gradients) against the
+oracle, element by element, on seeded inputs that span several 64-point
+tiles and a ragged tail."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from workloads import SEEDS, precision_stress_points, standard_normal_points
+
+from _gpu_common import TOL, assert_close_per_l, host_points, to_dev
+
+pytestmark = pytest.mark.gpu
+
+LMAXES = [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 13, 16, 17, 20, 24, 25, 32]
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("normalize", [False, True])
+@pytest.mark.parametrize("l_max", LMAXES)
+def test_forward_matches_oracle(l_max, normalize, dtype):
+    import paper_2302_08381_amd as sph
+    print(f"forward l_max={l_max} normalize={normalize} dtype={dtype}", flush=True)
+    n = 200  # 3 full tiles + a ragged tail of 8
+    pts = standard_normal_points(n, 100 + l_max)
+    xyz = to_dev(pts, dtype)
+    Y, dY = sph.sph_compute_with_gradients(xyz, l_max, normalize)
+    Yo = sph.sph_compute(xyz, l_max, normalize)
+    torch.cuda.synchronize()
+    # the value-only path runs the same value pass
+    assert torch.equal(Y, Yo)
+    hp = host_points(xyz)
+    Yr, Gr = oracle.real_sph(hp, l_max, normalize)
+    tol = TOL[dtype]
+    assert_close_per_l(Y.cpu().numpy(), Yr, hp, l_max, normalize, "Y", tol)
+    assert_close_per_l(dY.cpu().numpy(), Gr, hp, l_max, normalize, "dY", tol)
+
+
+@pytest.mark.parametrize("normalize", [False, True])
+def test_plain_cpu_workload_float64(normalize):
+    """N = 1000 standard-normal points, float64, l_max = 4 (both kinds)."""
+    import paper_2302_08381_amd as sph
+    pts = standard_normal_points(1000, SEEDS["plain_cpu"])
+    xyz = to_dev(pts, torch.float64)
+    Y, dY = sph.sph_compute_with_gradients(xyz, 4, normalize)
+    Yr, Gr = oracle.real_sph(pts, 4, normalize)
+    assert_close_per_l(Y.cpu().numpy(), Yr, pts, 4, normalize, "Y", 1e-12)
+    assert_close_per_l(dY.cpu().numpy(), Gr, pts, 4, normalize, "dY", 1e-12)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_full_size_l8_sampled(dtype):
+    """N = 1e6 standard-normal points, l_max = 8, normalised: the benchmark's
+    launch; 4096 sampled rows against the oracle, plus the addition theorem
+    on every row."""
+    import paper_2302_08381_amd as sph
+    n = 1_000_000
+    pts = standard_normal_points(n, SEEDS["plain_gpu"])
+    xyz = to_dev(pts, dtype)
+    Y, dY = sph.sph_compute_with_gradients(xyz, 8, True)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(7)
+    idx = np.sort(rng.choice(n, 4096, replace=False))
+    idx = np.concatenate([idx, [0, 63, 64, n - 1]])
+    hp = host_points(xyz[torch.as_tensor(idx, device=xyz.device)])
+    Yr, Gr = oracle.real_sph(hp, 8, True)
+    ii = torch.as_tensor(idx, device=xyz.device)
+    assert_close_per_l(Y[ii].cpu().numpy(), Yr, hp, 8, True, "Y", TOL[dtype])
+    assert_close_per_l(dY[ii].cpu().numpy(), Gr, hp, 8, True, "dY", TOL[dtype])
+    # sum_m Y_lm^2 = (2l+1)/(4 pi) for every point
+    Yd = Y.double()
+    for l in range(9):
+        s = (Yd[:, l * l:(l + 1) ** 2] ** 2).sum(1)
+        ref = (2 * l + 1) / (4 * np.pi)
+        assert float((s / ref - 1).abs().max()) < (1e-5 if dtype == torch.float32 else 1e-12)
+
+
+def test_edge_cases():
+    import paper_2302_08381_amd as sph
+    for dtype in (torch.float32, torch.float64):
+        # n = 0
+        e = torch.empty((0, 3), dtype=dtype, device="cuda")
+        assert sph.sph_compute(e, 5, True).shape == (0, 36)
+        # n = 1, origin, exact poles, a point on each axis
+        pts = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 1.5], [0.0, 0.0, -0.25], [2.0, 0.0, 0.0],
+                        [0.0, -3.0, 0.0], [1e-30, 0.0, 1.0]])
+        for normalize in (False, True):
+            for L in (0, 1, 5, 8, 20):
+                for n in (1, len(pts)):
+                    xyz = to_dev(pts[:n], dtype)
+                    Y, dY = sph.sph_compute_with_gradients(xyz, L, normalize)
+                    hp = host_points(xyz)
+                    Yr, Gr = oracle.real_sph(hp, L, normalize)
+                    assert torch.isfinite(Y).all() and torch.isfinite(dY).all()
+                    assert_close_per_l(Y.cpu().numpy(), Yr, hp, L, normalize, "Y", TOL[dtype])
+                    assert_close_per_l(dY.cpu().numpy(), Gr, hp, L, normalize, "dY", TOL[dtype])
+
+
+def test_nan_propagates_and_neighbours_unaffected():
+    import paper_2302_08381_amd as sph
+    pts = standard_normal_points(70, 9)
+    pts[5] = [np.nan, 0.2, 0.3]
+    xyz = to_dev(pts, torch.float32)
+    Y, dY = sph.sph_compute_with_gradients(xyz, 6, True)
+    assert torch.isnan(Y[5, 1:]).all()
+    ok = torch.ones(70, dtype=torch.bool)
+    ok[5] = False
+    assert torch.isfinite(Y[ok.cuda()]).all() and torch.isfinite(dY[ok.cuda()]).all()
+
+
+def test_unaligned_buffers_take_the_scalar_path():
+    """Outputs that start 4 bytes past a 16-byte boundary."""
+    import paper_2302_08381_amd as sph
+    n, L = 150, 8
+    K = (L + 1) ** 2
+    pts = standard_normal_points(n, 11)
+    xyz = to_dev(pts, torch.float32)
+    bigY = torch.zeros(n * K + 1, dtype=torch.float32, device="cuda")
+    Y = bigY[1:].view(n, K)
+    sph.sph_compute(xyz, L, True, Y=Y)
+    Yref = sph.sph_compute(xyz, L, True)
+    assert torch.equal(Y, Yref)
+
+
+def test_deterministic():
+    import paper_2302_08381_amd as sph
+    xyz = to_dev(standard_normal_points(5000, 12), torch.float32)
+    a = sph.sph_compute_with_gradients(xyz, 12, False)
+    b = sph.sph_compute_with_gradients(xyz, 12, False)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_precision_stress_l32(dtype):
+    """l_max = 32, normalised: unit sphere, points within 1e-12..1e-3 of the
+    z axis, and radii 1e-6..1e3; per-l error per sub-population."""
+    import paper_2302_08381_amd as sph
+    pts, cls = precision_stress_points(4000, SEEDS["precision"])
+    xyz = to_dev(pts, dtype)
+    Y, dY = sph.sph_compute_with_gradients(xyz, 32, True)
+    hp = host_points(xyz)
+    Yr, Gr = oracle.real_sph(hp, 32, True)
+    Yc, dYc = Y.cpu().numpy(), dY.cpu().numpy()
+    for c in range(3):
+        m = cls == c
+        mx, _ = oracle.per_l_errors(Yc[m], Yr[m], hp[m], 32, True, "Y")
+        assert mx.max() <= TOL[dtype], (c, mx)
+        mx, _ = oracle.per_l_errors(dYc[m], Gr[m], hp[m], 32, True, "dY")
+        assert mx.max() <= TOL[dtype], (c, mx)
