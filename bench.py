@@ -1,0 +1,234 @@
+"""Throughput of the spherical-harmonics hot path on one MI355X.
+
+One step = the forward with gradients (Y[N,81] and dY[N,3,81] from xyz[N,3],
+sph_compute_with_gradients) followed by the backward (grad_xyz[N,3] from the
+stored dY and an upstream gradient grad_Y[N,81], sph_backward), for
+N = 1,000,000 points with iid N(0,1) coordinates, l_max = 8, float32,
+normalised harmonics.  Inputs are resident in HBM before timing starts.
+
+Prints ONE JSON line:  points/s (value), ms per step, the roofline of the
+dominant kernel (algorithmic bytes per launch / mean launch time from HIP
+events recorded around each launch on the launch stream), the per-kernel
+figures, the accuracy of sampled rows against the float64 oracle, and the
+oracle itself timed on the host cores (a bounded sample).
+
+    python bench.py [--gpus 1] [--steps 50] [--warmup 10] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+N_POINTS = 1_000_000
+L_MAX = 8
+NORMALIZE = True
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+METRIC = "points/s and HBM GB/s for Y+dY fwd+bwd, l_max=8 FP32; max err vs FP64 oracle"
+KERNEL_SOURCES = ["sph_device.hpp", "sph_coeffs.hpp", "sph_fwd.inl", "sph_fwd4.inl", "sph_bwd.inl", "sph_launch.hpp",
+                  "sph_instances.inl", "sph_api.cpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_l8_f32.json")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2302_08381_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kind: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None if absent or taken on different kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    k = t.get("kernels", {}).get(kind)
+    return None if k is None else float(k["hbm_bytes_per_launch"])
+
+
+def cpu_baseline(n_sample: int = 200_000, chunk: int = 20_000):
+    """The oracle (longdouble, single thread) on the first n_sample points of
+    the same workload: forward with gradients plus the backward contraction."""
+    import numpy as np
+
+    import oracle
+    from workloads import SEEDS, standard_normal, standard_normal_points
+
+    pts = standard_normal_points(N_POINTS, SEEDS["plain_gpu"])[:n_sample].astype(np.float32)
+    K = (L_MAX + 1) ** 2
+    gY = standard_normal((N_POINTS, K), SEEDS["plain_gpu_grad"])[:n_sample].astype(np.float32)
+    t0 = time.perf_counter()
+    for s in range(0, n_sample, chunk):
+        _, G = oracle.real_sph(pts[s:s + chunk], L_MAX, NORMALIZE)
+        oracle.backward(G, gY[s:s + chunk])
+    dt = time.perf_counter() - t0
+    return {"value": n_sample / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n_sample} of the {N_POINTS} points, Y+dY and backward, "
+                      f"numpy longdouble recurrence tier, {dt:.1f} s wall, 1 thread"}
+
+
+def accuracy(xyz, Y, dY, gY, gx, rows: int = 2048):
+    import numpy as np
+    import torch
+
+    import oracle
+    rng = np.random.default_rng(7)
+    idx = np.sort(rng.choice(xyz.shape[0], rows, replace=False))
+    ii = torch.as_tensor(idx, device=xyz.device)
+    hp = xyz[ii].double().cpu().numpy()
+    Yr, Gr = oracle.real_sph(hp, L_MAX, NORMALIZE)
+    my, _ = oracle.per_l_errors(Y[ii].cpu().numpy(), Yr, hp, L_MAX, NORMALIZE, "Y")
+    md, _ = oracle.per_l_errors(dY[ii].cpu().numpy(), Gr, hp, L_MAX, NORMALIZE, "dY")
+    gYh = gY[ii].double().cpu().numpy()
+    ref = np.asarray(oracle.backward(Gr, gYh), float)
+    _, g, _ = oracle.component_scales(hp, L_MAX, NORMALIZE)
+    mb = float((np.abs(gx[ii].double().cpu().numpy() - ref) / (np.abs(gYh) * g).sum(1)[:, None]).max())
+    return {"rows_checked": rows, "Y_max_scaled_err": float(my.max()), "dY_max_scaled_err": float(md.max()),
+            "grad_xyz_max_scaled_err": mb, "tolerance": 1e-5}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="only run warmup + steps (and a 1 GiB reference copy), for rocprofv3")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path has no "
+              "cross-GPU step and this build runs on a single MI355X.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2302_08381_amd as sph
+    from workloads import SEEDS, standard_normal, standard_normal_points
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    K = (L_MAX + 1) ** 2
+    xyz = torch.as_tensor(standard_normal_points(N_POINTS, SEEDS["plain_gpu"]), dtype=torch.float32).to(dev)
+    gY = torch.as_tensor(standard_normal((N_POINTS, K), SEEDS["plain_gpu_grad"]), dtype=torch.float32).to(dev)
+    Y = torch.empty((N_POINTS, K), dtype=torch.float32, device=dev)
+    dY = torch.empty((N_POINTS, 3, K), dtype=torch.float32, device=dev)
+    gx = torch.empty((N_POINTS, 3), dtype=torch.float32, device=dev)
+
+    def step():
+        sph.sph_compute_with_gradients(xyz, L_MAX, NORMALIZE, Y=Y, dY=dY)
+        sph.sph_backward(dY, gY, L_MAX, grad_xyz=gx)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    if args.profile:
+        for _ in range(args.steps):
+            step()
+        # reference copy of known size for scaling the HBM byte counters
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_run": True, "steps": args.steps, "reference_copy_bytes": 2 * a.numel() * 4}))
+        return
+
+    stream = torch.cuda.current_stream(dev)  # the launch stream of both kernels
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        ev[s][0].record(stream)
+        sph.sph_compute_with_gradients(xyz, L_MAX, NORMALIZE, Y=Y, dY=dY)
+        ev[s][1].record(stream)
+        sph.sph_backward(dY, gY, L_MAX, grad_xyz=gx)
+        ev[s][2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t_fwd = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps * 1e-3
+    t_bwd = sum(e[1].elapsed_time(e[2]) for e in ev) / args.steps * 1e-3
+    ms_per_step = wall / args.steps * 1e3
+    value = N_POINTS * args.steps / wall
+
+    w = 4
+    bytes_fwd = N_POINTS * w * (3 + 4 * K)   # read xyz, write Y and dY
+    bytes_bwd = N_POINTS * w * (4 * K + 3)   # read dY and grad_Y, write grad_xyz
+    per_kernel = {
+        "forward_Y_dY": {"kernel": "k_fwd4<float,8,8,true>", "mean_s": t_fwd, "bytes": bytes_fwd,
+                         "GB_per_s": bytes_fwd / t_fwd / 1e9, "traffic": load_traffic("forward")},
+        "backward": {"kernel": "k_bwd<float>", "mean_s": t_bwd, "bytes": bytes_bwd,
+                     "GB_per_s": bytes_bwd / t_bwd / 1e9, "traffic": load_traffic("backward")},
+    }
+    dom_name = max(per_kernel, key=lambda k: per_kernel[k]["mean_s"])
+    dom = per_kernel[dom_name]
+    achieved = dom["GB_per_s"]
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": dom["traffic"], "kernel": dom_name}
+
+    # practical ceilings on this GPU: torch's write-only fill and copy kernels
+    # over buffers of the forward's size
+    big = torch.empty(bytes_fwd // 4, dtype=torch.float32, device=dev)
+    half = torch.empty(bytes_fwd // 8, dtype=torch.float32, device=dev)
+    half2 = torch.empty_like(half)
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    for _ in range(3):
+        big.fill_(1.0)
+        half2.copy_(half)
+    e0.record(stream)
+    for _ in range(10):
+        big.fill_(1.0)
+    e1.record(stream)
+    for _ in range(10):
+        half2.copy_(half)
+    e2.record(stream)
+    torch.cuda.synchronize()
+    fill_gbs = bytes_fwd * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    copy_gbs = 2 * half.numel() * 4 * 10 / (e1.elapsed_time(e2) * 1e-3) / 1e9
+    del big, half, half2
+
+    acc = accuracy(xyz, Y, dY, gY, gx)
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "plain forward Y+dY then backward, N=1,000,000 points, xyz iid N(0,1) "
+                               "(seed 2), grad_Y iid N(0,1) (seed 12), l_max=8, normalize=true, float32",
+                   "n_points": N_POINTS, "l_max": L_MAX, "normalize": NORMALIZE},
+        "GB_per_s_fwd_bwd": round((bytes_fwd + bytes_bwd) * args.steps / wall / 1e9, 1),
+        "roofline": roofline,
+        "kernels": {k: {kk: (round(vv, 7) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                    for k, v in per_kernel.items()},
+        "ceilings_GB_per_s": {"torch_fill_write_only": round(fill_gbs, 1), "torch_copy": round(copy_gbs, 1)},
+        "accuracy": acc,
+        "kernel_sources": kernel_hash(),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -136,8 +136,8 @@ int32_t sph_double_backward(const void* xyz, const void* grad_Y, const void* v,
  * the neighbours of each selected atom).  Every output follows the
  * concatenated row order.  The launch is a persistent kernel replayed from a
  * cached hipGraph; on the first call for a (dtype, l_max, normalize, outputs)
- * combination the library times its launch variants on the caller's own
- * buffers and keeps the fastest (the timing synchronises the host once).
+ * combination the library times the persistent-grid sizes on the caller's
+ * own buffers and keeps the fastest (the timing synchronises the host once).
  *   xyz        in  [n_points,3]
  *   offsets    in  int64 [n_env+1], DEVICE memory
  *   n_env      number of environments (>= 0)
@@ -161,15 +161,16 @@ int32_t sph_batched_compute(const void* xyz, const int64_t* offsets, int64_t n_e
 /*
  * sph_batched_set_options -- batched-path controls (process-wide).
  *   use_graph  1: replay cached hipGraphs (default); 0: plain launches
- *   autotune   1: time the launch variants on first use (default);
+ *   autotune   1: time the persistent-grid sizes on first use (default);
  *              0: use the built-in defaults
  */
 int32_t sph_batched_set_options(int32_t use_graph, int32_t autotune);
 
 /*
- * sph_batched_get_config -- the launch variant chosen for a combination, as
- * "variant=<i> blocks_per_cu=<b> budget=<e>" in buf (NUL-terminated, at most
- * len bytes).  Returns SPH_ERR_INVALID if nothing was chosen yet.
+ * sph_batched_get_config -- the launch shape chosen for a combination, as
+ * "blocks_per_cu=<b> tile_points=<t>" in buf (NUL-terminated, at most len
+ * bytes); blocks_per_cu = 0 means one tile per block.  Returns
+ * SPH_ERR_INVALID if nothing was chosen yet.
  */
 int32_t sph_batched_get_config(int32_t l_max, int32_t normalize, int32_t dtype,
                                int32_t store_dY, int32_t with_backward,

@@ -23,8 +23,15 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsph.so")
 
 ARCH = os.environ.get("SPH_OFFLOAD_ARCH", "gfx950")
-SOURCES = ["sph_kernels_fwd_f32.hip", "sph_kernels_fwd_f64.hip", "sph_kernels_bwd_f32.hip",
-           "sph_kernels_bwd_f64.hip", "sph_api.cpp"]
+SOURCES = [
+    "sph_kernels_fwd_f32_n0.hip",
+    "sph_kernels_fwd_f32_n1.hip",
+    "sph_kernels_bwd_f32.hip",
+    "sph_kernels_fwd_f64_n0.hip",
+    "sph_kernels_fwd_f64_n1.hip",
+    "sph_kernels_bwd_f64.hip",
+    "sph_api.cpp",
+]
 COMMON = [
     "-O3", "-std=c++20", "-fPIC", "-Wall",
     # packed FP32 instructions stay off (plain float code only)

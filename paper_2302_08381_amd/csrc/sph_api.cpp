@@ -74,8 +74,15 @@ int32_t check_no_overlap(std::initializer_list<Range> outs, std::initializer_lis
   return SPH_OK;
 }
 
-sph::KernelInfo fwd_info(int32_t dtype, int L, int norm, int variant) {
-  return dtype == SPH_F64 ? sph::fwd_info_f64(L, norm, variant) : sph::fwd_info_f32(L, norm, variant);
+// derivs = 0: values-only kernel; 1: the four-lanes-per-point kernel that
+// also emits derivatives (and fuses the backward).
+sph::KernelInfo fwd_info(int32_t dtype, int L, int norm, int derivs) {
+  if (dtype == SPH_F64) {
+    if (derivs) return norm ? sph::fwd_derivs_f64_n1(L) : sph::fwd_derivs_f64_n0(L);
+    return norm ? sph::fwd_values_f64_n1(L) : sph::fwd_values_f64_n0(L);
+  }
+  if (derivs) return norm ? sph::fwd_derivs_f32_n1(L) : sph::fwd_derivs_f32_n0(L);
+  return norm ? sph::fwd_values_f32_n1(L) : sph::fwd_values_f32_n0(L);
 }
 sph::KernelInfo bwd_info(int32_t dtype, int L) {
   return dtype == SPH_F64 ? sph::bwd_info_f64(L) : sph::bwd_info_f32(L);
@@ -129,8 +136,9 @@ struct BatchKey {
   }
 };
 
+// Persistent-grid size: blocks_per_cu * CUs blocks loop over the tiles;
+// 0 means one tile per block (a plain grid).
 struct Choice {
-  int variant = 0;
   int blocks_per_cu = 8;
 };
 
@@ -150,7 +158,7 @@ int g_use_graph = 1;
 int g_autotune = 1;
 bool g_cache_loaded = false;
 
-constexpr int kBpcCandidates[] = {2, 4, 8, 16};
+constexpr int kBpcCandidates[] = {2, 4, 8, 16, 0};
 
 std::string cache_path() {
   const char* p = std::getenv("SPH_AUTOTUNE_CACHE");
@@ -158,7 +166,7 @@ std::string cache_path() {
 }
 
 // Cache file: one line per combination,
-//   dtype L normalize store_dY backward variant blocks_per_cu
+//   dtype L normalize store_dY backward blocks_per_cu
 // Unreadable or malformed lines are ignored (defaults apply).
 void load_cache_locked() {
   if (g_cache_loaded) return;
@@ -169,12 +177,12 @@ void load_cache_locked() {
   std::string line;
   while (std::getline(f, line)) {
     std::istringstream is(line);
-    int dt, L, nm, sd, bw, v, b;
-    if (!(is >> dt >> L >> nm >> sd >> bw >> v >> b)) continue;
-    if (dt < 0 || dt > 1 || L < 0 || L > sph::kMaxLmax || v < 0 || v >= sph::kNumBudgetVariants ||
-        b < 1 || b > 64)
+    int dt, L, nm, sd, bw, b;
+    if (!(is >> dt >> L >> nm >> sd >> bw >> b)) continue;
+    if (dt < 0 || dt > 1 || L < 0 || L > sph::kMaxLmax || nm < 0 || nm > 1 || sd < 0 || sd > 1 || bw < 0 ||
+        bw > 1 || b < 0 || b > 64)
       continue;
-    for (int dev = 0; dev < 64; ++dev) g_choice[BatchKey{dev, dt, L, nm, sd, bw}] = Choice{v, b};
+    for (int dev = 0; dev < 64; ++dev) g_choice[BatchKey{dev, dt, L, nm, sd, bw}] = Choice{b};
   }
 }
 
@@ -186,46 +194,43 @@ void save_cache_locked() {
   for (const auto& kv : g_choice) {
     if (kv.first.dev != 0) continue;
     f << kv.first.dtype << ' ' << kv.first.L << ' ' << kv.first.norm << ' ' << kv.first.store_dy << ' '
-      << kv.first.bwd << ' ' << kv.second.variant << ' ' << kv.second.blocks_per_cu << '\n';
+      << kv.first.bwd << ' ' << kv.second.blocks_per_cu << '\n';
   }
 }
 
-size_t batched_lds(const sph::KernelInfo& ki, bool bwd) { return ki.tile_lds_bytes * (bwd ? 2 : 1); }
+unsigned batched_grid(const sph::KernelInfo& ki, int64_t n, int bpc) {
+  const int64_t tiles = ceil_div(n, ki.tile_points);
+  const int64_t g = bpc > 0 ? std::min<int64_t>(tiles, int64_t(num_cus()) * bpc) : tiles;
+  return static_cast<unsigned>(std::max<int64_t>(1, g));
+}
 
-// Times every (variant, blocks_per_cu) on the caller's buffers (the kernel
-// is a pure function of its inputs, so repeated runs leave the right
-// result) and returns the fastest.  Synchronises the host.
-Choice autotune(int32_t dtype, int L, int norm, sph::FwdParams params, bool bwd, hipStream_t s) {
+// Times every persistent-grid size on the caller's buffers (the kernel is a
+// pure function of its inputs, so repeated runs leave the right result) and
+// returns the fastest.  Synchronises the host.
+Choice autotune(const sph::KernelInfo& ki, size_t lds, sph::FwdParams params, hipStream_t s) {
   Choice best;
   float best_ms = 1e30f;
-  const int cus = num_cus();
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return best;
   if (hipEventCreate(&e1) != hipSuccess) {
     (void)hipEventDestroy(e0);
     return best;
   }
-  const int64_t tiles = ceil_div(params.n, sph::kPointsPerBlock);
-  for (int v = 0; v < sph::kNumBudgetVariants; ++v) {
-    const sph::KernelInfo ki = fwd_info(dtype, L, norm, v);
-    const size_t lds = batched_lds(ki, bwd);
-    if (ki.fn == nullptr || ensure_lds(ki.fn, lds) != hipSuccess) continue;
-    for (int bpc : kBpcCandidates) {
-      const unsigned grid = static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(tiles, int64_t(cus) * bpc)));
-      sph::FwdParams p = params;
-      if (launch(ki.fn, grid, sph::kBlock, lds, &p, s) != hipSuccess) continue;  // warm-up
-      (void)hipEventRecord(e0, s);
-      constexpr int reps = 3;
-      bool okr = true;
-      for (int r = 0; r < reps && okr; ++r) okr = launch(ki.fn, grid, sph::kBlock, lds, &p, s) == hipSuccess;
-      (void)hipEventRecord(e1, s);
-      if (!okr || hipEventSynchronize(e1) != hipSuccess) continue;
-      float ms = 0;
-      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) continue;
-      if (ms < best_ms) {
-        best_ms = ms;
-        best = Choice{v, bpc};
-      }
+  for (int bpc : kBpcCandidates) {
+    const unsigned grid = batched_grid(ki, params.n, bpc);
+    sph::FwdParams p = params;
+    if (launch(ki.fn, grid, sph::kBlock, lds, &p, s) != hipSuccess) continue;  // warm-up
+    (void)hipEventRecord(e0, s);
+    constexpr int reps = 3;
+    bool okr = true;
+    for (int r = 0; r < reps && okr; ++r) okr = launch(ki.fn, grid, sph::kBlock, lds, &p, s) == hipSuccess;
+    (void)hipEventRecord(e1, s);
+    if (!okr || hipEventSynchronize(e1) != hipSuccess) continue;
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) continue;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = Choice{bpc};
     }
   }
   (void)hipEventDestroy(e0);
@@ -272,14 +277,14 @@ int32_t sph_compute_with_gradients(const void* xyz, int64_t n, int32_t l_max, in
                              {{xyz, un * 3 * w, "xyz"}, {Y, un * K * w, "Y"}, {dY, un * 3 * K * w, "dY"}})) !=
       SPH_OK)
     return st;
-  const sph::KernelInfo ki = fwd_info(dtype, l_max, normalize, 0);
+  const sph::KernelInfo ki = fwd_info(dtype, l_max, normalize, dY != nullptr ? 1 : 0);
   if (ki.fn == nullptr) return fail(SPH_ERR_INVALID, "no kernel for these arguments");
-  hipError_t e = ensure_lds(ki.fn, ki.tile_lds_bytes);
+  hipError_t e = ensure_lds(ki.fn, ki.lds_bytes);
   if (e != hipSuccess) return device_fail(e, "hipFuncSetAttribute");
   sph::FwdParams p{xyz, n, l_max, Y, dY, nullptr, nullptr, nullptr, 0, nullptr};
-  const int64_t grid = ceil_div(n, sph::kPointsPerBlock);
+  const int64_t grid = ceil_div(n, ki.tile_points);
   if (grid > 0x7fffffff) return fail(SPH_ERR_INVALID, "n too large for one launch");
-  e = launch(ki.fn, static_cast<unsigned>(grid), sph::kBlock, ki.tile_lds_bytes, &p,
+  e = launch(ki.fn, static_cast<unsigned>(grid), sph::kBlock, ki.lds_bytes, &p,
              static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return device_fail(e, "forward launch");
   return ok();
@@ -332,12 +337,12 @@ int32_t sph_double_backward(const void* xyz, const void* grad_Y, const void* v, 
     return st;
   const sph::KernelInfo ki = dbwd_info(dtype, l_max, normalize);
   if (ki.fn == nullptr) return fail(SPH_ERR_INVALID, "no kernel for these arguments");
-  hipError_t e = ensure_lds(ki.fn, ki.tile_lds_bytes);
+  hipError_t e = ensure_lds(ki.fn, ki.lds_bytes);
   if (e != hipSuccess) return device_fail(e, "hipFuncSetAttribute");
   sph::DbwdParams p{xyz, grad_Y, v, n, l_max, grad_grad_Y, grad_xyz2};
   const int64_t grid = ceil_div(n, sph::kPointsPerBlock);
   if (grid > 0x7fffffff) return fail(SPH_ERR_INVALID, "n too large for one launch");
-  e = launch(ki.fn, static_cast<unsigned>(grid), sph::kBlock, ki.tile_lds_bytes, &p,
+  e = launch(ki.fn, static_cast<unsigned>(grid), sph::kBlock, ki.lds_bytes, &p,
              static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return device_fail(e, "double backward launch");
   return ok();
@@ -360,9 +365,9 @@ int32_t sph_batched_get_config(int32_t l_max, int32_t normalize, int32_t dtype, 
   std::lock_guard<std::mutex> lk(g_batch_mu);
   auto it = g_choice.find(BatchKey{dev, dtype, l_max, normalize, store_dY ? 1 : 0, with_backward ? 1 : 0});
   if (it == g_choice.end()) return fail(SPH_ERR_INVALID, "no configuration chosen yet");
-  const sph::KernelInfo ki = fwd_info(dtype, l_max, normalize, it->second.variant);
-  std::snprintf(buf, static_cast<size_t>(len), "variant=%d blocks_per_cu=%d budget=%d", it->second.variant,
-                it->second.blocks_per_cu, ki.budget);
+  const sph::KernelInfo ki = fwd_info(dtype, l_max, normalize, (store_dY || with_backward) ? 1 : 0);
+  std::snprintf(buf, static_cast<size_t>(len), "blocks_per_cu=%d tile_points=%d", it->second.blocks_per_cu,
+                ki.tile_points);
   return ok();
 }
 
@@ -401,6 +406,12 @@ int32_t sph_batched_compute(const void* xyz, const int64_t* offsets, int64_t n_e
   const BatchKey key{dev, dtype, l_max, normalize, dY != nullptr ? 1 : 0, bwd ? 1 : 0};
   sph::FwdParams p{xyz, n_points, l_max, Y, dY, grad_Y, grad_xyz, offsets, n_env, status};
 
+  const sph::KernelInfo ki = fwd_info(dtype, l_max, normalize, (dY != nullptr || bwd) ? 1 : 0);
+  if (ki.fn == nullptr) return fail(SPH_ERR_INVALID, "no kernel for these arguments");
+  const size_t lds = bwd ? ki.lds_bytes_bwd : ki.lds_bytes;
+  e = ensure_lds(ki.fn, lds);
+  if (e != hipSuccess) return device_fail(e, "hipFuncSetAttribute");
+
   std::lock_guard<std::mutex> lk(g_batch_mu);
   load_cache_locked();
   Choice ch;
@@ -408,21 +419,13 @@ int32_t sph_batched_compute(const void* xyz, const int64_t* offsets, int64_t n_e
   if (it != g_choice.end()) {
     ch = it->second;
   } else if (g_autotune && !capturing && n_points >= int64_t(64) * 256) {
-    ch = autotune(dtype, l_max, normalize, p, bwd, s);
+    ch = autotune(ki, lds, p, s);
     g_choice[key] = ch;
     save_cache_locked();
   } else {
     g_choice[key] = ch;
   }
-
-  const sph::KernelInfo ki = fwd_info(dtype, l_max, normalize, ch.variant);
-  if (ki.fn == nullptr) return fail(SPH_ERR_INVALID, "no kernel for these arguments");
-  const size_t lds = batched_lds(ki, bwd);
-  e = ensure_lds(ki.fn, lds);
-  if (e != hipSuccess) return device_fail(e, "hipFuncSetAttribute");
-  const int64_t tiles = ceil_div(n_points, sph::kPointsPerBlock);
-  const unsigned grid = static_cast<unsigned>(
-      std::max<int64_t>(1, std::min<int64_t>(tiles, int64_t(num_cus()) * ch.blocks_per_cu)));
+  const unsigned grid = batched_grid(ki, n_points, ch.blocks_per_cu);
 
   if (!g_use_graph || capturing) {
     e = launch(ki.fn, grid, sph::kBlock, lds, &p, s);

@@ -48,6 +48,7 @@ __global__ __launch_bounds__(kWave) void k_bwd(BwdParams P) {
       const T* d0 = sd + (3 * pl) * S;
       const T* d1 = d0 + S;
       const T* d2 = d1 + S;
+#pragma unroll 4
       for (int k = q; k < cnt; k += 4) {
         const T gv = g[k];
         a0 += gv * d0[k];

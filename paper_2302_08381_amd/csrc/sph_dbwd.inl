@@ -46,12 +46,12 @@ __device__ __forceinline__ void dbwd_group(const Point<T>& pt, T vx, T vy, T vz,
   const T rho = ex * vx + ey * vy;
   const T uv = rho + ez * vz;  // u.v (normalised: ex = u)
   T pp[MM + 3], prev[MM + 3], cur[MM + 3];
-  q_row<T, MM>(la - 2, ez, pt.rxy2, pp);
-  q_row<T, MM>(la - 1, ez, pt.rxy2, prev);
+  q_row_rt<T, MM>(la - 2, ez, pt.rxy2, pp);
+  q_row_rt<T, MM>(la - 1, ez, pt.rxy2, prev);
   T* row = st + lane * S - kb;
 #pragma unroll 1
   for (int l = la; l < lb; ++l) {
-    q_row<T, MM>(l, ez, pt.rxy2, cur);
+    q_row_rt<T, MM>(l, ez, pt.rxy2, cur);
     const int k0 = l * l + l;
     T Sgv = T(0), Sgx = T(0), Sgy = T(0), Sgz = T(0), Sy = T(0);
     auto process = [&](int k, T Yt, T gx, T gy, T gz, T gv, T hx, T hy, T hz) {
@@ -77,7 +77,7 @@ __device__ __forceinline__ void dbwd_group(const Point<T>& pt, T vx, T vy, T vz,
     T s0 = T(0), c0 = T(1);  // s_m, c_m
 #pragma unroll
     for (int m = 0; m <= MM; ++m) {
-      if (m > l) break;
+      if (m > l) continue;  // no early exit: keeps the loop fully unrolled
       if (m > 0) {
         const T sn = ex * s0 + ey * c0;
         const T cn = ex * c0 - ey * s0;
@@ -143,8 +143,8 @@ __device__ __forceinline__ void dbwd_group(const Point<T>& pt, T vx, T vy, T vz,
       A.hy += -fl * (Sgy * uv + ey * Sgv) - fl * Sy * vy + a * ey;
       A.hz += -fl * (Sgz * uv + ez * Sgv) - fl * Sy * vz + a * ez;
     }
-    copy_row<T, MM>(l - 1, prev, pp);
-    copy_row<T, MM>(l, cur, prev);
+    copy_row<T, MM>(MM, prev, pp);
+    copy_row<T, MM>(MM, cur, prev);
   }
 }
 

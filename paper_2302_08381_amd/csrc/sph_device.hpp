@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
+#include <utility>
 
 #include "sph_coeffs.hpp"
 
@@ -135,12 +137,41 @@ __device__ __forceinline__ void q_row(int l, T z, T rxy2, T (&q)[MM + 3]) {
   }
 }
 
+// The same row for a run-time degree, without branches: every slot m <= MM
+// is computed (the folded coefficients are 0 for m >= l, so slots past the
+// row come out 0) and the row start is a select.  Branches on a run-time
+// degree here would make the compiler merge the stores into a dynamically
+// indexed one and move the row to scratch memory.
+template <typename T, int MM>
+__device__ __forceinline__ void q_row_rt(int l, T z, T rxy2, T (&q)[MM + 3]) {
+  const CoefTable<T>& C = coef<T>();
+  const T qll = (l >= 0) ? C.qll[l < 0 ? 0 : l] : T(0);
+  const int li = l < 0 ? 0 : l;
+  q[MM + 1] = T(0);
+  q[MM + 2] = T(0);
+#pragma unroll
+  for (int m = MM; m >= 0; --m) {
+    const T t = (C.b1[li][m] * z) * q[m + 1] + (C.b2[li][m] * rxy2) * q[m + 2];
+    q[m] = (m == l) ? qll : t;
+  }
+}
+
+// Row of either kind: compile-time degrees take the branchy form (it folds),
+// run-time degrees the branch-free one.
+template <typename T, int MM, bool CT>
+__device__ __forceinline__ void q_row_any(int l, T z, T rxy2, T (&q)[MM + 3]) {
+  if constexpr (CT)
+    q_row<T, MM>(l, z, rxy2, q);
+  else
+    q_row_rt<T, MM>(l, z, rxy2, q);
+}
+
 // dst[m] = src[m] for m <= l.
 template <typename T, int MM>
 __device__ __forceinline__ void copy_row(int l, const T (&src)[MM + 3], T (&dst)[MM + 3]) {
 #pragma unroll
   for (int m = 0; m <= MM; ++m) {
-    if (m > l) break;
+    if (m > l) continue;  // no early exit: keeps the loop fully unrolled
     dst[m] = src[m];
   }
 }
@@ -167,7 +198,7 @@ __device__ __forceinline__ void emit_row(int l, const T (&prev)[MM + 3], const T
   T s = T(0), c = T(1);    // s_m, c_m
 #pragma unroll
   for (int m = 0; m <= MM; ++m) {
-    if (m > l) break;
+    if (m > l) continue;  // no early exit: keeps the loop fully unrolled
     if (m > 0) {
       const T sn = ex * s + ey * c;
       const T cn = ex * c - ey * s;
@@ -250,21 +281,33 @@ __device__ __forceinline__ Point<T> make_point(T x, T y, T z) {
 }
 
 // ------------------------------------------------------------ LDS <-> global
-// Copy a staged tile out: for point p < np and j < cnt,
-//   dst[p * gstride + j] = st[p * S + j].
-// With gstride == cnt == S (one contiguous block) and 16-byte aligned dst the
-// copy uses 16-byte vector accesses.
+// Copies between an LDS tile (rows of stride S) and global rows (stride
+// gstride): for row p < rows and j < cnt, dst[p * gstride + j] <-> st[p * S + j].
+// With gstride == cnt == S (one contiguous block) and a 16-byte aligned
+// global pointer the copy uses 16-byte accesses.  Each lane keeps kBatch
+// accesses in flight before it waits, so LDS and memory latency is paid once
+// per batch rather than once per element.
+constexpr int kBatch = 4;
+
 template <typename T>
 __device__ __forceinline__ void copy_out(const T* __restrict__ st, int S, T* __restrict__ dst,
-                                         int gstride, int cnt, int np, int lane, bool vec) {
-  const int total = np * cnt;
+                                         int gstride, int cnt, int rows, int lane, bool vec) {
+  const int total = rows * cnt;
   if (vec && gstride == cnt && S == cnt) {
     using V = typename Vec16<T>::type;
     constexpr int W = Vec16<T>::n;
     const int nv = total / W;
     const V* sv = reinterpret_cast<const V*>(st);
     V* dv = reinterpret_cast<V*>(dst);
-    for (int i = lane; i < nv; i += kWave) __builtin_nontemporal_store(sv[i], dv + i);
+    for (int i0 = lane; i0 < nv; i0 += kWave * kBatch) {
+      V v[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u)
+        if (i0 + u * kWave < nv) v[u] = sv[i0 + u * kWave];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u)
+        if (i0 + u * kWave < nv) __builtin_nontemporal_store(v[u], dv + i0 + u * kWave);
+    }
     for (int j = nv * W + lane; j < total; j += kWave) __builtin_nontemporal_store(st[j], dst + j);
     return;
   }
@@ -272,29 +315,45 @@ __device__ __forceinline__ void copy_out(const T* __restrict__ st, int S, T* __r
   int k = lane - p * cnt;
   const int qs = kWave / cnt;
   const int rs = kWave - qs * cnt;
-  for (int j = lane; j < total; j += kWave) {
-    __builtin_nontemporal_store(st[p * S + k], dst + (p * gstride + k));
-    p += qs;
-    k += rs;
-    if (k >= cnt) {
-      k -= cnt;
-      ++p;
+  for (int j0 = lane; j0 < total; j0 += kWave * kBatch) {
+    T v[kBatch];
+    int off[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      off[u] = p * gstride + k;
+      if (j0 + u * kWave < total) v[u] = st[p * S + k];
+      p += qs;
+      k += rs;
+      if (k >= cnt) {
+        k -= cnt;
+        ++p;
+      }
     }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+      if (j0 + u * kWave < total) __builtin_nontemporal_store(v[u], dst + off[u]);
   }
 }
 
-// The reverse: st[p * S + j] = src[p * gstride + j].
 template <typename T>
 __device__ __forceinline__ void copy_in(T* __restrict__ st, int S, const T* __restrict__ src,
-                                        int gstride, int cnt, int np, int lane, bool vec) {
-  const int total = np * cnt;
+                                        int gstride, int cnt, int rows, int lane, bool vec) {
+  const int total = rows * cnt;
   if (vec && gstride == cnt && S == cnt) {
     using V = typename Vec16<T>::type;
     constexpr int W = Vec16<T>::n;
     const int nv = total / W;
     V* sv = reinterpret_cast<V*>(st);
     const V* dv = reinterpret_cast<const V*>(src);
-    for (int i = lane; i < nv; i += kWave) sv[i] = __builtin_nontemporal_load(dv + i);
+    for (int i0 = lane; i0 < nv; i0 += kWave * kBatch) {
+      V v[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u)
+        if (i0 + u * kWave < nv) v[u] = __builtin_nontemporal_load(dv + i0 + u * kWave);
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u)
+        if (i0 + u * kWave < nv) sv[i0 + u * kWave] = v[u];
+    }
     for (int j = nv * W + lane; j < total; j += kWave) st[j] = __builtin_nontemporal_load(src + j);
     return;
   }
@@ -302,14 +361,23 @@ __device__ __forceinline__ void copy_in(T* __restrict__ st, int S, const T* __re
   int k = lane - p * cnt;
   const int qs = kWave / cnt;
   const int rs = kWave - qs * cnt;
-  for (int j = lane; j < total; j += kWave) {
-    st[p * S + k] = __builtin_nontemporal_load(src + (p * gstride + k));
-    p += qs;
-    k += rs;
-    if (k >= cnt) {
-      k -= cnt;
-      ++p;
+  for (int j0 = lane; j0 < total; j0 += kWave * kBatch) {
+    T v[kBatch];
+    int off[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      off[u] = p * S + k;
+      if (j0 + u * kWave < total) v[u] = __builtin_nontemporal_load(src + (p * gstride + k));
+      p += qs;
+      k += rs;
+      if (k >= cnt) {
+        k -= cnt;
+        ++p;
+      }
     }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+      if (j0 + u * kWave < total) st[off[u]] = v[u];
   }
 }
 

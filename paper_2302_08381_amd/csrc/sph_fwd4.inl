@@ -1,0 +1,215 @@
+// Forward with derivatives, four lanes per point.
+//
+// A wave takes 16 points; lane 4p + r of the wave evaluates point p and emits
+// component r of it: r = 0 the values, r = 1, 2, 3 the d/dx, d/dy, d/dz
+// derivatives.  Every lane runs the same instructions (the four components
+// differ only in per-lane weights, so nothing diverges):
+//
+//   value(+m) = A c_m + B P+ ,  value(-m) = A s_m + B P-
+//   A = w_q Qt_l^m + w_t Tm + w_c Cm        (Tm = gxy Qt_{l-1}^{m+1}, Cm = gz Qt_{l-1}^m)
+//   B = w_b m Qt_l^m,  P+ = a1 c_{m-1} + a2 s_{m-1},  P- = a1 s_{m-1} - a2 c_{m-1}
+//
+// with (w_q, w_t, w_c, w_b, a1, a2) = (1, 0, 0, 0, -, -) for the values,
+// (0, x, 0, 1, 1, 0) for d/dx, (0, y, 0, 1, 0, -1) for d/dy and
+// (0, 0, 1, 0, -, -) for d/dz, which restates Eqs. real-sh-cartesian and
+// iter-deri with the product rule.  For the normalised harmonics the chain
+// rule (d_a Yt(u) - l u_a Yt(u)) / r folds into A -> (A - l u_a Qt) / r and
+// B -> B / r.
+//
+// The LDS tile is laid out exactly as the global arrays: 16 value rows
+// (the points' Y rows) followed by 48 derivative rows (dY[p][a]); with one
+// group of degrees both blocks are contiguous in global memory and are
+// copied out with 16-byte stores.  The fused backward (batched entry) adds
+// sum_k gY[p,k] dY[p,a,k] in lane 4p + a + 1, which then owns grad_xyz[p,a].
+#pragma once
+
+#include "sph_device.hpp"
+#include "sph_fwd.inl"
+#include "sph_launch.hpp"
+
+namespace sph {
+
+constexpr int kQuadPoints = 16;
+
+// Per-point LDS budget (elements of one component of one group of degrees).
+template <typename T>
+inline constexpr int kQuadBudget = 84;
+template <>
+inline constexpr int kQuadBudget<double> = 42;
+
+template <typename T>
+struct Role {
+  T wq, wt, wc, wb, a1, a2;  // weights of the unified formula
+  T lu;                      // u_a (normalised; times l per degree), 0 for the values
+  T sc;                      // 1/r for normalised derivatives, else 1
+};
+
+template <typename T, bool NORM>
+__device__ __forceinline__ Role<T> make_role(int r, const Point<T>& pt) {
+  Role<T> ro;
+  ro.wq = (r == 0) ? T(1) : T(0);
+  ro.wt = (r == 1) ? pt.ex : ((r == 2) ? pt.ey : T(0));
+  ro.wc = (r == 3) ? T(1) : T(0);
+  ro.a1 = (r == 1) ? T(1) : T(0);
+  ro.a2 = (r == 2) ? T(-1) : T(0);
+  T sc = T(1);
+  T lu = T(0);
+  if constexpr (NORM) {
+    if (r != 0) {
+      sc = pt.inv_r;
+      lu = (r == 1) ? pt.ex : ((r == 2) ? pt.ey : pt.ez);
+    }
+  }
+  ro.wb = (r == 1 || r == 2) ? sc : T(0);
+  ro.sc = sc;
+  ro.lu = lu;
+  return ro;
+}
+
+// Emit degrees [la, lb) of this lane's component into row[k] (row is the
+// lane's LDS row shifted by -kb).  UNROLL: the degree loop has compile-time
+// bounds and is unrolled.
+template <typename T, int MM, bool NORM>
+__device__ __forceinline__ void emit4_row(int l, const Role<T>& ro, const Point<T>& pt,
+                                          const T (&prev)[MM + 3], const T (&cur)[MM + 3], T* row) {
+  const CoefTable<T>& C = coef<T>();
+  constexpr T kIS2 = T(kInvSqrt2d);
+  const int k0 = l * l + l;
+  T lu = T(0);
+  if constexpr (NORM) lu = T(l) * ro.lu;
+  T sp = T(0), cp = T(1);
+  T s = T(0), c = T(1);
+#pragma unroll
+  for (int m = 0; m <= MM; ++m) {
+    if (m > l) continue;  // no early exit: keeps the loop fully unrolled
+    if (m > 0) {
+      const T sn = pt.ex * s + pt.ey * c;
+      const T cn = pt.ex * c - pt.ey * s;
+      sp = s;
+      cp = c;
+      s = sn;
+      c = cn;
+    }
+    const T q = cur[m];
+    const T Tm = (m <= l - 2) ? C.gxy[l][m] * prev[m + 1] : T(0);
+    const T Cm = (m <= l - 1) ? C.gz[l][m] * prev[m] : T(0);
+    T A = q * ro.wq + Tm * ro.wt + Cm * ro.wc;
+    if constexpr (NORM) A = (A - lu * q) * ro.sc;
+    if (m == 0) {
+      row[k0] = A * kIS2;
+    } else {
+      const T B = q * (T(m) * ro.wb);
+      const T Pp = cp * ro.a1 + sp * ro.a2;
+      const T Pm = sp * ro.a1 - cp * ro.a2;
+      row[k0 + m] = A * c + B * Pp;
+      row[k0 - m] = A * s + B * Pm;
+    }
+  }
+}
+
+// Emit degrees [la, lb) of this lane's component into row[k] (row is the
+// lane's LDS row shifted by -kb).  UNROLL: the degree loop has compile-time
+// bounds and is unrolled.
+template <typename T, int MM, bool NORM, bool UNROLL>
+__device__ __forceinline__ void emit4(const Role<T>& ro, const Point<T>& pt, int la, int lb, T* row) {
+  constexpr int UR = UNROLL ? 64 : 1;
+  T prev[MM + 3], cur[MM + 3];
+  q_row_any<T, MM, UNROLL>(la - 1, pt.ez, pt.rxy2, prev);
+#pragma unroll UR
+  for (int l = la; l < lb; ++l) {
+    q_row_any<T, MM, UNROLL>(l, pt.ez, pt.rxy2, cur);
+    emit4_row<T, MM, NORM>(l, ro, pt, prev, cur, row);
+    copy_row<T, MM>(UNROLL ? l : MM, cur, prev);
+  }
+}
+
+template <typename T, int MM, bool NORM, bool UNROLL>
+__device__ __forceinline__ void fwd4_group(const Role<T>& ro, const Point<T>& pt, int la, int lb, int K,
+                                           int64_t p0, int np, int lane, int lrow, const FwdParams& P,
+                                           T* st, T* sg, T& acc) {
+  const int kb = la * la;
+  const int cnt = lb * lb - kb;
+  const int S = cnt | 1;
+  const bool bwd = P.gY != nullptr;
+  const int p = lane >> 2;
+  if (bwd) {
+    const T* src = static_cast<const T*>(P.gY) + p0 * K + kb;
+    copy_in(sg, S, src, K, cnt, np, lane, aligned16(src));
+  }
+  emit4<T, MM, NORM, UNROLL>(ro, pt, la, lb, st + lrow * S - kb);
+  __syncthreads();
+  if (bwd) {
+    // derivative lanes: sum_k gY[p,k] dY[p,a,k] over this group
+    const T* gr = sg + p * S;
+    const T* dr = st + lrow * S;
+    T s0 = T(0), s1 = T(0);
+    int j = 0;
+    for (; j + 1 < cnt; j += 2) {
+      s0 += gr[j] * dr[j];
+      s1 += gr[j + 1] * dr[j + 1];
+    }
+    if (j < cnt) s0 += gr[j] * dr[j];
+    acc += s0 + s1;
+  }
+  {
+    T* dst = static_cast<T*>(P.Y) + p0 * K + kb;
+    copy_out(st, S, dst, K, cnt, np, lane, aligned16(dst));
+  }
+  if (P.dY != nullptr) {
+    T* dst = static_cast<T*>(P.dY) + p0 * 3 * K + kb;
+    copy_out(st + kQuadPoints * S, S, dst, K, cnt, 3 * np, lane, aligned16(dst));
+  }
+  __syncthreads();
+}
+
+// LT >= 0: l_max = LT known at compile time (MM = LT, degree loops unrolled);
+// LT < 0: l_max = P.L <= MM at run time.  Dynamic LDS: 64 rows of
+// stride(L) elements, plus 16 rows for the upstream-gradient tile when the
+// backward is fused.
+template <typename T, int MM, int LT, bool NORM>
+__global__ __launch_bounds__(kWave) void k_fwd4(FwdParams P) {
+  constexpr int B = kQuadBudget<T>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int lane = threadIdx.x;
+  const int L = LT >= 0 ? LT : P.L;
+  const int K = (L + 1) * (L + 1);
+  const int smax = plan_stride(L, B);
+  T* st = reinterpret_cast<T*>(smem);
+  T* sg = st + kWave * smax;
+  const int p = lane >> 2;
+  const int r = lane & 3;
+  const int lrow = (r == 0) ? p : kQuadPoints + 3 * p + (r - 1);
+
+  if (P.status != nullptr && blockIdx.x == 0) check_offsets(P, lane);
+
+  const T* xyz = static_cast<const T*>(P.xyz);
+  for (int64_t tile = blockIdx.x; tile * kQuadPoints < P.n; tile += gridDim.x) {
+    const int64_t p0 = tile * kQuadPoints;
+    const int np = static_cast<int>(P.n - p0 < kQuadPoints ? P.n - p0 : kQuadPoints);
+    T x = T(0), y = T(0), z = T(0);
+    if (p < np) {
+      const T* q = xyz + (p0 + p) * 3;
+      x = q[0];
+      y = q[1];
+      z = q[2];
+    }
+    const Point<T> pt = make_point<T, NORM>(x, y, z);
+    const Role<T> ro = make_role<T, NORM>(r, pt);
+    T acc = T(0);
+    if constexpr (LT >= 0) {
+      constexpr Plan PL = make_plan(LT, B);
+#pragma unroll
+      for (int g = 0; g < PL.ng; ++g)
+        fwd4_group<T, MM, NORM, true>(ro, pt, PL.lo[g], PL.hi[g], K, p0, np, lane, lrow, P, st, sg, acc);
+    } else {
+      for (int la = 0; la <= L;) {
+        const int lb = group_end(la, L, B);
+        fwd4_group<T, MM, NORM, false>(ro, pt, la, lb, K, p0, np, lane, lrow, P, st, sg, acc);
+        la = lb;
+      }
+    }
+    if (P.gY != nullptr && r > 0 && p < np) static_cast<T*>(P.gxyz)[(p0 + p) * 3 + (r - 1)] = acc;
+  }
+}
+
+}  // namespace sph

@@ -1,4 +1,4 @@
-// backward and double backward kernels, float
+// backward and double-backward kernels, float
 #define SPH_T float
 #define SPH_SUFFIX f32
 #define SPH_FAMILY 2

@@ -1,4 +1,4 @@
-// backward and double backward kernels, double
+// backward and double-backward kernels, double
 #define SPH_T double
 #define SPH_SUFFIX f64
 #define SPH_FAMILY 2

@@ -44,23 +44,30 @@ struct DbwdParams {
   void* gxyz2; // nullable
 };
 
-// Number of LDS budget variants per forward kernel (autotuner choice).
-constexpr int kNumBudgetVariants = 2;
-
-// A kernel's host stub, the LDS bytes of one 64-point staging tile for the
-// l_max it was looked up with (forward: the launch passes one tile, or two
-// with the fused backward, as dynamic LDS; double backward: one tile;
-// backward: static LDS, 0), and the per-point LDS budget in elements.
+// A kernel's host stub, its dynamic LDS bytes (for the l_max it was looked
+// up with), and for the forward with derivatives the LDS bytes when the
+// backward is fused (the extra upstream-gradient tile); tile_points is the
+// number of points one block covers per tile.
 struct KernelInfo {
   const void* fn;
-  size_t tile_lds_bytes;
-  int budget;
+  size_t lds_bytes;
+  size_t lds_bytes_bwd;
+  int tile_points;
 };
 
-// Per element type (suffix f32 / f64).  The kernel serves every l_max up to
-// its m-extent bucket.  fn == nullptr when the arguments are out of range.
-KernelInfo fwd_info_f32(int L, int normalize, int variant);
-KernelInfo fwd_info_f64(int L, int normalize, int variant);
+// Per element type (suffix f32 / f64) and normalisation; fn == nullptr when
+// the arguments are out of range.
+//   values:      Y only (one lane per point, 64-point tiles)
+//   derivatives: Y and dY and/or the fused backward (four lanes per point,
+//                16-point tiles)
+KernelInfo fwd_values_f32_n0(int L);
+KernelInfo fwd_values_f32_n1(int L);
+KernelInfo fwd_values_f64_n0(int L);
+KernelInfo fwd_values_f64_n1(int L);
+KernelInfo fwd_derivs_f32_n0(int L);
+KernelInfo fwd_derivs_f32_n1(int L);
+KernelInfo fwd_derivs_f64_n0(int L);
+KernelInfo fwd_derivs_f64_n1(int L);
 KernelInfo bwd_info_f32(int L);
 KernelInfo bwd_info_f64(int L);
 KernelInfo dbwd_info_f32(int L, int normalize);

@@ -27,11 +27,12 @@ def test_forward_matches_oracle(l_max, normalize, dtype):
     Y, dY = sph.sph_compute_with_gradients(xyz, l_max, normalize)
     Yo = sph.sph_compute(xyz, l_max, normalize)
     torch.cuda.synchronize()
-    # the value-only path runs the same value pass
-    assert torch.equal(Y, Yo)
     hp = host_points(xyz)
     Yr, Gr = oracle.real_sph(hp, l_max, normalize)
     tol = TOL[dtype]
+    # the values-only kernel (one lane per point) and the derivative kernel
+    # (four lanes per point) both against the oracle
+    assert_close_per_l(Yo.cpu().numpy(), Yr, hp, l_max, normalize, "Y", tol)
     assert_close_per_l(Y.cpu().numpy(), Yr, hp, l_max, normalize, "Y", tol)
     assert_close_per_l(dY.cpu().numpy(), Gr, hp, l_max, normalize, "dY", tol)
 
