@@ -127,6 +127,33 @@ hipError_t launch(const void* fn, unsigned grid, unsigned block, size_t lds, voi
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Grid of a plain forward call: as many blocks as can be resident at once
+// (occupancy from the runtime for this kernel and LDS size), each looping
+// over tiles; never more blocks than tiles.
+std::mutex g_occ_mu;
+std::map<std::tuple<int, const void*, size_t>, int> g_occ;
+
+int64_t resident_grid(const void* fn, size_t lds, int64_t tiles) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  int per_cu = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_occ_mu);
+    auto key = std::make_tuple(dev, fn, lds);
+    auto it = g_occ.find(key);
+    if (it != g_occ.end()) {
+      per_cu = it->second;
+    } else {
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, sph::kBlock, lds) != hipSuccess ||
+          per_cu <= 0)
+        per_cu = 4;
+      (void)hipGetLastError();
+      g_occ[key] = per_cu;
+    }
+  }
+  return std::max<int64_t>(1, std::min<int64_t>(tiles, int64_t(num_cus()) * per_cu));
+}
+
 // ------------------------------------------------------------ batched path
 struct BatchKey {
   int dev, dtype, L, norm, store_dy, bwd;
@@ -282,8 +309,7 @@ int32_t sph_compute_with_gradients(const void* xyz, int64_t n, int32_t l_max, in
   hipError_t e = ensure_lds(ki.fn, ki.lds_bytes);
   if (e != hipSuccess) return device_fail(e, "hipFuncSetAttribute");
   sph::FwdParams p{xyz, n, l_max, Y, dY, nullptr, nullptr, nullptr, 0, nullptr};
-  const int64_t grid = ceil_div(n, ki.tile_points);
-  if (grid > 0x7fffffff) return fail(SPH_ERR_INVALID, "n too large for one launch");
+  const int64_t grid = resident_grid(ki.fn, ki.lds_bytes, ceil_div(n, ki.tile_points));
   e = launch(ki.fn, static_cast<unsigned>(grid), sph::kBlock, ki.lds_bytes, &p,
              static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return device_fail(e, "forward launch");

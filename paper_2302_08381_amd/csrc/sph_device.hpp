@@ -381,6 +381,34 @@ __device__ __forceinline__ void copy_in(T* __restrict__ st, int S, const T* __re
   }
 }
 
+// Full-tile contiguous copy with compile-time size: NV 16-byte vectors from
+// LDS to global, kBatchFull in flight per lane, no predication except on the
+// last, partial sweep.
+constexpr int kBatchFull = 8;
+
+template <typename T, int NV>
+__device__ __forceinline__ void copy_out_full(const T* __restrict__ st, T* __restrict__ dst, int lane) {
+  using V = typename Vec16<T>::type;
+  const V* sv = reinterpret_cast<const V*>(st);
+  V* dv = reinterpret_cast<V*>(dst);
+  constexpr int kSweeps = (NV + kWave - 1) / kWave;
+#pragma unroll
+  for (int s0 = 0; s0 < kSweeps; s0 += kBatchFull) {
+    V v[kBatchFull];
+#pragma unroll
+    for (int u = 0; u < kBatchFull; ++u) {
+      const int sw = s0 + u;
+      if (sw < kSweeps && (sw < NV / kWave || lane + sw * kWave < NV)) v[u] = sv[lane + sw * kWave];
+    }
+#pragma unroll
+    for (int u = 0; u < kBatchFull; ++u) {
+      const int sw = s0 + u;
+      if (sw < kSweeps && (sw < NV / kWave || lane + sw * kWave < NV))
+        __builtin_nontemporal_store(v[u], dv + lane + sw * kWave);
+    }
+  }
+}
+
 __device__ __forceinline__ bool aligned16(const void* p) {
   return (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
 }

@@ -38,6 +38,39 @@ __device__ __forceinline__ void emit_values(const Point<T>& pt, int la, int lb, 
   }
 }
 
+template <typename T, int MM, bool NORM, int LA, int LB>
+__device__ __forceinline__ void values_group_ct(const Point<T>& pt, int K, int64_t p0, int np, int lane,
+                                                const FwdParams& P, T* st) {
+  constexpr int kb = LA * LA;
+  constexpr int cnt = LB * LB - kb;
+  constexpr int S = cnt | 1;
+  T* row = st + lane * S - kb;
+  T cur[MM + 3], unused[MM + 3];
+#pragma unroll
+  for (int l = LA; l < LB; ++l) {
+    q_row<T, MM>(l, pt.ez, pt.rxy2, cur);
+    emit_row<T, MM, 0, NORM>(l, unused, cur, pt.ex, pt.ey, pt.ez, pt.inv_r, [&](int k, T v) { row[k] = v; });
+  }
+  __syncthreads();
+  T* dst = static_cast<T*>(P.Y) + p0 * K + kb;
+  if constexpr (S == cnt && kb == 0) {
+    if (np == kWave && aligned16(dst)) {
+      copy_out_full<T, kWave * cnt / Vec16<T>::n>(st, dst, lane);
+      __syncthreads();
+      return;
+    }
+  }
+  copy_out(st, S, dst, K, cnt, np, lane, aligned16(dst));
+  __syncthreads();
+}
+
+template <typename T, int MM, bool NORM, int LT, int... Gs>
+__device__ __forceinline__ void values_groups_ct(std::integer_sequence<int, Gs...>, const Point<T>& pt, int K,
+                                                 int64_t p0, int np, int lane, const FwdParams& P, T* st) {
+  constexpr Plan PL = make_plan(LT, kValueBudget<T>);
+  (values_group_ct<T, MM, NORM, PL.lo[Gs], PL.hi[Gs]>(pt, K, p0, np, lane, P, st), ...);
+}
+
 // LT >= 0: l_max = LT at compile time (MM = LT); LT < 0: l_max = P.L <= MM.
 // Dynamic LDS: 64 rows of stride(L) elements.
 template <typename T, int MM, int LT, bool NORM>
@@ -52,16 +85,25 @@ __global__ __launch_bounds__(kWave) void k_fwd(FwdParams P) {
   if (P.status != nullptr && blockIdx.x == 0) check_offsets(P, lane);
 
   const T* xyz = static_cast<const T*>(P.xyz);
-  for (int64_t tile = blockIdx.x; tile * kWave < P.n; tile += gridDim.x) {
-    const int64_t p0 = tile * kWave;
-    const int np = static_cast<int>(P.n - p0 < kWave ? P.n - p0 : kWave);
-    T x = T(0), y = T(0), z = T(0);
-    if (lane < np) {
-      const T* q = xyz + (p0 + lane) * 3;
+  // The coordinates of the block's next tile are loaded while the current
+  // tile is processed.
+  auto load_point = [&](int64_t tile, T& x, T& y, T& z) {
+    const int64_t i = tile * kWave + lane;
+    x = y = z = T(0);
+    if (i < P.n) {
+      const T* q = xyz + i * 3;
       x = q[0];
       y = q[1];
       z = q[2];
     }
+  };
+  T nx, ny, nz;
+  load_point(blockIdx.x, nx, ny, nz);
+  for (int64_t tile = blockIdx.x; tile * kWave < P.n; tile += gridDim.x) {
+    const int64_t p0 = tile * kWave;
+    const int np = static_cast<int>(P.n - p0 < kWave ? P.n - p0 : kWave);
+    const T x = nx, y = ny, z = nz;
+    load_point(tile + gridDim.x, nx, ny, nz);
     const Point<T> pt = make_point<T, NORM>(x, y, z);
     auto group = [&](int la, int lb, auto unroll_c) {
       constexpr bool UN = decltype(unroll_c)::value;
@@ -76,8 +118,7 @@ __global__ __launch_bounds__(kWave) void k_fwd(FwdParams P) {
     };
     if constexpr (LT >= 0) {
       constexpr Plan PL = make_plan(LT, B);
-#pragma unroll
-      for (int g = 0; g < PL.ng; ++g) group(PL.lo[g], PL.hi[g], std::true_type{});
+      values_groups_ct<T, MM, NORM, LT>(std::make_integer_sequence<int, PL.ng>{}, pt, K, p0, np, lane, P, st);
     } else {
       for (int la = 0; la <= L;) {
         const int lb = group_end(la, L, B);

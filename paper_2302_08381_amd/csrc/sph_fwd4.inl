@@ -123,6 +123,20 @@ __device__ __forceinline__ void emit4(const Role<T>& ro, const Point<T>& pt, int
   }
 }
 
+// Degrees [LA, LB) known at compile time: the degree loop unrolls fully and
+// every coefficient is a literal.
+template <typename T, int MM, bool NORM, int LA, int LB>
+__device__ __forceinline__ void emit4_ct(const Role<T>& ro, const Point<T>& pt, T* row) {
+  T prev[MM + 3], cur[MM + 3];
+  if constexpr (LA >= 1) q_row<T, MM>(LA - 1, pt.ez, pt.rxy2, prev);
+#pragma unroll
+  for (int l = LA; l < LB; ++l) {
+    q_row<T, MM>(l, pt.ez, pt.rxy2, cur);
+    emit4_row<T, MM, NORM>(l, ro, pt, prev, cur, row);
+    copy_row<T, MM>(l, cur, prev);
+  }
+}
+
 template <typename T, int MM, bool NORM, bool UNROLL>
 __device__ __forceinline__ void fwd4_group(const Role<T>& ro, const Point<T>& pt, int la, int lb, int K,
                                            int64_t p0, int np, int lane, int lrow, const FwdParams& P,
@@ -162,6 +176,59 @@ __device__ __forceinline__ void fwd4_group(const Role<T>& ro, const Point<T>& pt
   __syncthreads();
 }
 
+// One compile-time group of degrees [LA, LB): sizes are constants, full
+// tiles go out through the unpredicated fixed-size copy.
+template <typename T, int MM, bool NORM, int LA, int LB>
+__device__ __forceinline__ void fwd4_group_ct(const Role<T>& ro, const Point<T>& pt, int K, int64_t p0, int np,
+                                              int lane, int lrow, const FwdParams& P, T* st, T* sg, T& acc) {
+  constexpr int kb = LA * LA;
+  constexpr int cnt = LB * LB - kb;
+  constexpr int S = cnt | 1;
+  const bool bwd = P.gY != nullptr;
+  const int p = lane >> 2;
+  if (bwd) {
+    const T* src = static_cast<const T*>(P.gY) + p0 * K + kb;
+    copy_in(sg, S, src, K, cnt, np, lane, aligned16(src));
+  }
+  emit4_ct<T, MM, NORM, LA, LB>(ro, pt, st + lrow * S - kb);
+  __syncthreads();
+  if (bwd) {
+    const T* gr = sg + p * S;
+    const T* dr = st + lrow * S;
+    T s0 = T(0), s1 = T(0);
+#pragma unroll
+    for (int j = 0; j + 1 < cnt; j += 2) {
+      s0 += gr[j] * dr[j];
+      s1 += gr[j + 1] * dr[j + 1];
+    }
+    if constexpr (cnt % 2 == 1) s0 += gr[cnt - 1] * dr[cnt - 1];
+    acc += s0 + s1;
+  }
+  constexpr int W = Vec16<T>::n;
+  T* ydst = static_cast<T*>(P.Y) + p0 * K + kb;
+  T* ddst = P.dY != nullptr ? static_cast<T*>(P.dY) + p0 * 3 * K + kb : nullptr;
+  if constexpr (S == cnt && kb == 0) {  // one group of degrees: contiguous tiles
+    const bool full = np == kQuadPoints && aligned16(ydst) && (ddst == nullptr || aligned16(ddst));
+    if (full) {
+      copy_out_full<T, kQuadPoints * cnt / W>(st, ydst, lane);
+      if (ddst != nullptr) copy_out_full<T, 3 * kQuadPoints * cnt / W>(st + kQuadPoints * S, ddst, lane);
+      __syncthreads();
+      return;
+    }
+  }
+  copy_out(st, S, ydst, K, cnt, np, lane, aligned16(ydst));
+  if (ddst != nullptr) copy_out(st + kQuadPoints * S, S, ddst, K, cnt, 3 * np, lane, aligned16(ddst));
+  __syncthreads();
+}
+
+template <typename T, int MM, bool NORM, int LT, int... Gs>
+__device__ __forceinline__ void fwd4_groups_ct(std::integer_sequence<int, Gs...>, const Role<T>& ro,
+                                               const Point<T>& pt, int K, int64_t p0, int np, int lane,
+                                               int lrow, const FwdParams& P, T* st, T* sg, T& acc) {
+  constexpr Plan PL = make_plan(LT, kQuadBudget<T>);
+  (fwd4_group_ct<T, MM, NORM, PL.lo[Gs], PL.hi[Gs]>(ro, pt, K, p0, np, lane, lrow, P, st, sg, acc), ...);
+}
+
 // LT >= 0: l_max = LT known at compile time (MM = LT, degree loops unrolled);
 // LT < 0: l_max = P.L <= MM at run time.  Dynamic LDS: 64 rows of
 // stride(L) elements, plus 16 rows for the upstream-gradient tile when the
@@ -183,24 +250,32 @@ __global__ __launch_bounds__(kWave) void k_fwd4(FwdParams P) {
   if (P.status != nullptr && blockIdx.x == 0) check_offsets(P, lane);
 
   const T* xyz = static_cast<const T*>(P.xyz);
-  for (int64_t tile = blockIdx.x; tile * kQuadPoints < P.n; tile += gridDim.x) {
-    const int64_t p0 = tile * kQuadPoints;
-    const int np = static_cast<int>(P.n - p0 < kQuadPoints ? P.n - p0 : kQuadPoints);
-    T x = T(0), y = T(0), z = T(0);
-    if (p < np) {
-      const T* q = xyz + (p0 + p) * 3;
+  // The coordinates of the block's next tile are loaded while the current
+  // tile is processed.
+  auto load_point = [&](int64_t tile, T& x, T& y, T& z) {
+    const int64_t i = tile * kQuadPoints + p;
+    x = y = z = T(0);
+    if (i < P.n) {
+      const T* q = xyz + i * 3;
       x = q[0];
       y = q[1];
       z = q[2];
     }
+  };
+  T nx, ny, nz;
+  load_point(blockIdx.x, nx, ny, nz);
+  for (int64_t tile = blockIdx.x; tile * kQuadPoints < P.n; tile += gridDim.x) {
+    const int64_t p0 = tile * kQuadPoints;
+    const int np = static_cast<int>(P.n - p0 < kQuadPoints ? P.n - p0 : kQuadPoints);
+    const T x = nx, y = ny, z = nz;
+    load_point(tile + gridDim.x, nx, ny, nz);
     const Point<T> pt = make_point<T, NORM>(x, y, z);
     const Role<T> ro = make_role<T, NORM>(r, pt);
     T acc = T(0);
     if constexpr (LT >= 0) {
       constexpr Plan PL = make_plan(LT, B);
-#pragma unroll
-      for (int g = 0; g < PL.ng; ++g)
-        fwd4_group<T, MM, NORM, true>(ro, pt, PL.lo[g], PL.hi[g], K, p0, np, lane, lrow, P, st, sg, acc);
+      fwd4_groups_ct<T, MM, NORM, LT>(std::make_integer_sequence<int, PL.ng>{}, ro, pt, K, p0, np, lane, lrow, P,
+                                      st, sg, acc);
     } else {
       for (int la = 0; la <= L;) {
         const int lb = group_end(la, L, B);

@@ -8,7 +8,7 @@ import torch
 import oracle
 from workloads import SEEDS, csr_environments, standard_normal
 
-from _gpu_common import TOL, host_points, to_dev
+from _gpu_common import TOL, assert_bitwise_equal, host_points, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -32,8 +32,8 @@ def test_batched_equals_plain_and_oracle(l_max):
     torch.cuda.synchronize()
     assert int(status.item()) == 0
     # same device function on the same point: bitwise equal values
-    assert torch.equal(out["Y"], Y)
-    assert torch.equal(out["dY"], dY)
+    assert_bitwise_equal(out["Y"], Y, "batched Y")
+    assert_bitwise_equal(out["dY"], dY, "batched dY")
     # fused backward sums in another order
     scale = (gY.abs().double()[:, None, :] * dY.abs().double()).sum(2) + 1e-30
     rel = ((out["grad_xyz"].double() - gx.double()).abs() / scale).max()
@@ -67,12 +67,15 @@ def test_batched_output_variants_and_graph_replay():
         c = sph.sph_batched_compute(xyz, _offsets(offs), L, True, store_dY=True)
         torch.cuda.synchronize()
         # values only: the same kernel as sph_compute, bitwise
-        assert a["dY"] is None and a["grad_xyz"] is None and torch.equal(a["Y"], Yv)
+        assert a["dY"] is None and a["grad_xyz"] is None
+        assert_bitwise_equal(a["Y"], Yv, "batched values")
         # the values-only and the derivative kernels agree to rounding
         assert float((Yv - Y).abs().max()) < 1e-14
-        assert b["dY"] is None and torch.equal(b["Y"], Y)
+        assert b["dY"] is None
+        assert_bitwise_equal(b["Y"], Y, "batched+bwd Y")
         assert float(((b["grad_xyz"] - gx).abs()).max()) < 1e-12 * float(gx.abs().max() + 1)
-        assert torch.equal(c["Y"], Y) and torch.equal(c["dY"], dY)
+        assert_bitwise_equal(c["Y"], Y, "batched Y (dY stored)")
+        assert_bitwise_equal(c["dY"], dY, "batched dY")
 
 
 def test_batched_without_graph_matches():
@@ -86,7 +89,8 @@ def test_batched_without_graph_matches():
     finally:
         sph.sph_batched_set_options(use_graph=True, autotune=True)
     torch.cuda.synchronize()
-    assert torch.equal(a["Y"], b["Y"]) and torch.equal(a["dY"], b["dY"])
+    assert_bitwise_equal(a["Y"], b["Y"], "graph vs direct Y")
+    assert_bitwise_equal(a["dY"], b["dY"], "graph vs direct dY")
 
 
 def test_batched_empty_environments_and_status():
@@ -103,7 +107,7 @@ def test_batched_empty_environments_and_status():
     out = sph.sph_batched_compute(xyz, _offsets(offs), 3, False, status=st)
     torch.cuda.synchronize()
     assert int(st.item()) == 0
-    assert torch.equal(out["Y"], sph.sph_compute(xyz, 3, False))  # same values-only kernel
+    assert_bitwise_equal(out["Y"], sph.sph_compute(xyz, 3, False), "batched vs plain values")
     # inconsistent offsets: decreasing, wrong start, wrong end
     for bad in (np.array([0, 5, 3, n]), np.array([1, 2, 3, n]), np.array([0, 1, 2, n + 1])):
         st.fill_(-1)
