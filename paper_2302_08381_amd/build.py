@@ -24,11 +24,23 @@ LIB = os.path.join(PKG, "libsph.so")
 
 ARCH = os.environ.get("SPH_OFFLOAD_ARCH", "gfx950")
 SOURCES = [
-    "sph_kernels_fwd_f32_n0.hip",
-    "sph_kernels_fwd_f32_n1.hip",
+    "sph_kernels_values_f32_n0.hip",
+    "sph_kernels_derivs_f32_n0_m0.hip",
+    "sph_kernels_derivs_f32_n0_m1.hip",
+    "sph_kernels_derivs_f32_n0_m2.hip",
+    "sph_kernels_values_f32_n1.hip",
+    "sph_kernels_derivs_f32_n1_m0.hip",
+    "sph_kernels_derivs_f32_n1_m1.hip",
+    "sph_kernels_derivs_f32_n1_m2.hip",
     "sph_kernels_bwd_f32.hip",
-    "sph_kernels_fwd_f64_n0.hip",
-    "sph_kernels_fwd_f64_n1.hip",
+    "sph_kernels_values_f64_n0.hip",
+    "sph_kernels_derivs_f64_n0_m0.hip",
+    "sph_kernels_derivs_f64_n0_m1.hip",
+    "sph_kernels_derivs_f64_n0_m2.hip",
+    "sph_kernels_values_f64_n1.hip",
+    "sph_kernels_derivs_f64_n1_m0.hip",
+    "sph_kernels_derivs_f64_n1_m1.hip",
+    "sph_kernels_derivs_f64_n1_m2.hip",
     "sph_kernels_bwd_f64.hip",
     "sph_api.cpp",
 ]
@@ -72,7 +84,7 @@ def _compile(src: str, force: bool) -> str:
 
 def build(force: bool = False, verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4, 16)) as ex:
         objs = list(ex.map(lambda s: _compile(s, force), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]

@@ -74,15 +74,22 @@ int32_t check_no_overlap(std::initializer_list<Range> outs, std::initializer_lis
   return SPH_OK;
 }
 
-// derivs = 0: values-only kernel; 1: the four-lanes-per-point kernel that
-// also emits derivatives (and fuses the backward).
-sph::KernelInfo fwd_info(int32_t dtype, int L, int norm, int derivs) {
-  if (dtype == SPH_F64) {
-    if (derivs) return norm ? sph::fwd_derivs_f64_n1(L) : sph::fwd_derivs_f64_n0(L);
-    return norm ? sph::fwd_values_f64_n1(L) : sph::fwd_values_f64_n0(L);
-  }
-  if (derivs) return norm ? sph::fwd_derivs_f32_n1(L) : sph::fwd_derivs_f32_n0(L);
-  return norm ? sph::fwd_values_f32_n1(L) : sph::fwd_values_f32_n0(L);
+// The forward kernel for a set of outputs: values only (one lane per point)
+// unless dY is stored or the backward is fused (four lanes per point).
+sph::KernelInfo fwd_info(int32_t dtype, int L, int norm, bool store_dy, bool fused) {
+  using KF = sph::KernelInfo (*)(int);
+  static constexpr KF kValues[2][2] = {{sph::fwd_values_f32_n0, sph::fwd_values_f32_n1},
+                                       {sph::fwd_values_f64_n0, sph::fwd_values_f64_n1}};
+  static constexpr KF kDerivs[2][2][sph::kNumDerivModes] = {
+      {{sph::fwd_derivs_f32_n0_m0, sph::fwd_derivs_f32_n0_m1, sph::fwd_derivs_f32_n0_m2},
+       {sph::fwd_derivs_f32_n1_m0, sph::fwd_derivs_f32_n1_m1, sph::fwd_derivs_f32_n1_m2}},
+      {{sph::fwd_derivs_f64_n0_m0, sph::fwd_derivs_f64_n0_m1, sph::fwd_derivs_f64_n0_m2},
+       {sph::fwd_derivs_f64_n1_m0, sph::fwd_derivs_f64_n1_m1, sph::fwd_derivs_f64_n1_m2}}};
+  const int d = dtype == SPH_F64 ? 1 : 0;
+  const int n = norm ? 1 : 0;
+  if (!store_dy && !fused) return kValues[d][n](L);
+  const int mode = !fused ? sph::kDerivStore : (store_dy ? sph::kDerivFusedStore : sph::kDerivFused);
+  return kDerivs[d][n][mode](L);
 }
 sph::KernelInfo bwd_info(int32_t dtype, int L) {
   return dtype == SPH_F64 ? sph::bwd_info_f64(L) : sph::bwd_info_f32(L);
@@ -304,7 +311,7 @@ int32_t sph_compute_with_gradients(const void* xyz, int64_t n, int32_t l_max, in
                              {{xyz, un * 3 * w, "xyz"}, {Y, un * K * w, "Y"}, {dY, un * 3 * K * w, "dY"}})) !=
       SPH_OK)
     return st;
-  const sph::KernelInfo ki = fwd_info(dtype, l_max, normalize, dY != nullptr ? 1 : 0);
+  const sph::KernelInfo ki = fwd_info(dtype, l_max, normalize, dY != nullptr, false);
   if (ki.fn == nullptr) return fail(SPH_ERR_INVALID, "no kernel for these arguments");
   hipError_t e = ensure_lds(ki.fn, ki.lds_bytes);
   if (e != hipSuccess) return device_fail(e, "hipFuncSetAttribute");
@@ -391,7 +398,7 @@ int32_t sph_batched_get_config(int32_t l_max, int32_t normalize, int32_t dtype, 
   std::lock_guard<std::mutex> lk(g_batch_mu);
   auto it = g_choice.find(BatchKey{dev, dtype, l_max, normalize, store_dY ? 1 : 0, with_backward ? 1 : 0});
   if (it == g_choice.end()) return fail(SPH_ERR_INVALID, "no configuration chosen yet");
-  const sph::KernelInfo ki = fwd_info(dtype, l_max, normalize, (store_dY || with_backward) ? 1 : 0);
+  const sph::KernelInfo ki = fwd_info(dtype, l_max, normalize, store_dY != 0, with_backward != 0);
   std::snprintf(buf, static_cast<size_t>(len), "blocks_per_cu=%d tile_points=%d", it->second.blocks_per_cu,
                 ki.tile_points);
   return ok();
@@ -432,7 +439,7 @@ int32_t sph_batched_compute(const void* xyz, const int64_t* offsets, int64_t n_e
   const BatchKey key{dev, dtype, l_max, normalize, dY != nullptr ? 1 : 0, bwd ? 1 : 0};
   sph::FwdParams p{xyz, n_points, l_max, Y, dY, grad_Y, grad_xyz, offsets, n_env, status};
 
-  const sph::KernelInfo ki = fwd_info(dtype, l_max, normalize, (dY != nullptr || bwd) ? 1 : 0);
+  const sph::KernelInfo ki = fwd_info(dtype, l_max, normalize, dY != nullptr, bwd);
   if (ki.fn == nullptr) return fail(SPH_ERR_INVALID, "no kernel for these arguments");
   const size_t lds = bwd ? ki.lds_bytes_bwd : ki.lds_bytes;
   e = ensure_lds(ki.fn, lds);

@@ -38,7 +38,7 @@ __device__ __forceinline__ void emit_values(const Point<T>& pt, int la, int lb, 
   }
 }
 
-template <typename T, int MM, bool NORM, int LA, int LB>
+template <typename T, int MM, bool NORM, bool FAST, int LA, int LB>
 __device__ __forceinline__ void values_group_ct(const Point<T>& pt, int K, int64_t p0, int np, int lane,
                                                 const FwdParams& P, T* st) {
   constexpr int kb = LA * LA;
@@ -53,26 +53,37 @@ __device__ __forceinline__ void values_group_ct(const Point<T>& pt, int K, int64
   }
   __syncthreads();
   T* dst = static_cast<T*>(P.Y) + p0 * K + kb;
-  if constexpr (S == cnt && kb == 0) {
-    if (np == kWave && aligned16(dst)) {
-      copy_out_full<T, kWave * cnt / Vec16<T>::n>(st, dst, lane);
-      __syncthreads();
-      return;
-    }
+  if constexpr (FAST) {
+    static_assert(S == cnt && kb == 0, "fast path needs one contiguous group");
+    copy_out_full<T, kWave * cnt / Vec16<T>::n>(st, dst, lane);
+  } else {
+    copy_out(st, S, dst, K, cnt, np, lane, aligned16(dst));
   }
-  copy_out(st, S, dst, K, cnt, np, lane, aligned16(dst));
   __syncthreads();
 }
 
-template <typename T, int MM, bool NORM, int LT, int... Gs>
+template <typename T, int MM, bool NORM, bool FAST, int LT, int... Gs>
 __device__ __forceinline__ void values_groups_ct(std::integer_sequence<int, Gs...>, const Point<T>& pt, int K,
                                                  int64_t p0, int np, int lane, const FwdParams& P, T* st) {
   constexpr Plan PL = make_plan(LT, kValueBudget<T>);
-  (values_group_ct<T, MM, NORM, PL.lo[Gs], PL.hi[Gs]>(pt, K, p0, np, lane, P, st), ...);
+  (values_group_ct<T, MM, NORM, FAST, PL.lo[Gs], PL.hi[Gs]>(pt, K, p0, np, lane, P, st), ...);
+}
+
+template <typename T, int LT>
+constexpr bool values_has_fast() {
+  if constexpr (LT < 0) {
+    return false;
+  } else {
+    constexpr Plan PL = make_plan(LT, kValueBudget<T>);
+    constexpr int K = (LT + 1) * (LT + 1);
+    return PL.ng == 1 && (K % 2 == 1);
+  }
 }
 
 // LT >= 0: l_max = LT at compile time (MM = LT); LT < 0: l_max = P.L <= MM.
-// Dynamic LDS: 64 rows of stride(L) elements.
+// Dynamic LDS: 64 rows of stride(L) elements.  Full tiles of a one-group
+// plan run one straight path with the next tile's coordinates loaded ahead
+// (see k_fwd4); the ragged tile and unaligned outputs take the general path.
 template <typename T, int MM, int LT, bool NORM>
 __global__ __launch_bounds__(kWave) void k_fwd(FwdParams P) {
   constexpr int B = kValueBudget<T>;
@@ -85,46 +96,60 @@ __global__ __launch_bounds__(kWave) void k_fwd(FwdParams P) {
   if (P.status != nullptr && blockIdx.x == 0) check_offsets(P, lane);
 
   const T* xyz = static_cast<const T*>(P.xyz);
-  // The coordinates of the block's next tile are loaded while the current
-  // tile is processed.
-  auto load_point = [&](int64_t tile, T& x, T& y, T& z) {
-    const int64_t i = tile * kWave + lane;
-    x = y = z = T(0);
-    if (i < P.n) {
-      const T* q = xyz + i * 3;
-      x = q[0];
-      y = q[1];
-      z = q[2];
-    }
-  };
-  T nx, ny, nz;
-  load_point(blockIdx.x, nx, ny, nz);
-  for (int64_t tile = blockIdx.x; tile * kWave < P.n; tile += gridDim.x) {
+  auto tile_body = [&](int64_t tile, T x, T y, T z, auto fast_c) {
+    constexpr bool FAST = decltype(fast_c)::value;
     const int64_t p0 = tile * kWave;
-    const int np = static_cast<int>(P.n - p0 < kWave ? P.n - p0 : kWave);
-    const T x = nx, y = ny, z = nz;
-    load_point(tile + gridDim.x, nx, ny, nz);
+    const int np = FAST ? kWave : static_cast<int>(P.n - p0 < kWave ? P.n - p0 : kWave);
     const Point<T> pt = make_point<T, NORM>(x, y, z);
-    auto group = [&](int la, int lb, auto unroll_c) {
-      constexpr bool UN = decltype(unroll_c)::value;
-      const int kb = la * la;
-      const int cnt = lb * lb - kb;
-      const int S = cnt | 1;
-      emit_values<T, MM, NORM, UN>(pt, la, lb, st + lane * S - kb);
-      __syncthreads();
-      T* dst = static_cast<T*>(P.Y) + p0 * K + kb;
-      copy_out(st, S, dst, K, cnt, np, lane, aligned16(dst));
-      __syncthreads();
-    };
     if constexpr (LT >= 0) {
       constexpr Plan PL = make_plan(LT, B);
-      values_groups_ct<T, MM, NORM, LT>(std::make_integer_sequence<int, PL.ng>{}, pt, K, p0, np, lane, P, st);
+      values_groups_ct<T, MM, NORM, FAST, LT>(std::make_integer_sequence<int, PL.ng>{}, pt, K, p0, np, lane, P,
+                                              st);
     } else {
       for (int la = 0; la <= L;) {
         const int lb = group_end(la, L, B);
-        group(la, lb, std::false_type{});
+        const int kb = la * la;
+        const int cnt = lb * lb - kb;
+        const int S = cnt | 1;
+        emit_values<T, MM, NORM, false>(pt, la, lb, st + lane * S - kb);
+        __syncthreads();
+        T* dst = static_cast<T*>(P.Y) + p0 * K + kb;
+        copy_out(st, S, dst, K, cnt, np, lane, aligned16(dst));
+        __syncthreads();
         la = lb;
       }
+    }
+  };
+  auto load_point = [&](int64_t i, T& x, T& y, T& z) {
+    const T* q = xyz + i * 3;
+    x = q[0];
+    y = q[1];
+    z = q[2];
+  };
+
+  constexpr bool kFast = values_has_fast<T, LT>();
+  if (kFast && aligned16(P.Y)) {
+    const int64_t nfull = P.n / kWave;
+    if (static_cast<int64_t>(blockIdx.x) < nfull) {
+      T nx, ny, nz;
+      load_point(blockIdx.x * kWave + lane, nx, ny, nz);
+      for (int64_t tile = blockIdx.x; tile < nfull; tile += gridDim.x) {
+        const T x = nx, y = ny, z = nz;
+        const int64_t nt = tile + gridDim.x < nfull ? tile + gridDim.x : tile;
+        load_point(nt * kWave + lane, nx, ny, nz);
+        tile_body(tile, x, y, z, std::integral_constant<bool, kFast>{});
+      }
+    }
+    if (P.n % kWave != 0 && nfull % gridDim.x == blockIdx.x) {
+      T x = T(0), y = T(0), z = T(0);
+      if (nfull * kWave + lane < P.n) load_point(nfull * kWave + lane, x, y, z);
+      tile_body(nfull, x, y, z, std::false_type{});
+    }
+  } else {
+    for (int64_t tile = blockIdx.x; tile * kWave < P.n; tile += gridDim.x) {
+      T x = T(0), y = T(0), z = T(0);
+      if (tile * kWave + lane < P.n) load_point(tile * kWave + lane, x, y, z);
+      tile_body(tile, x, y, z, std::false_type{});
     }
   }
 }

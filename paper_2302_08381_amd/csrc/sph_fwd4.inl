@@ -137,14 +137,14 @@ __device__ __forceinline__ void emit4_ct(const Role<T>& ro, const Point<T>& pt, 
   }
 }
 
-template <typename T, int MM, bool NORM, bool UNROLL>
+template <typename T, int MM, bool NORM, bool UNROLL, bool FUSED, bool STORE>
 __device__ __forceinline__ void fwd4_group(const Role<T>& ro, const Point<T>& pt, int la, int lb, int K,
                                            int64_t p0, int np, int lane, int lrow, const FwdParams& P,
                                            T* st, T* sg, T& acc) {
   const int kb = la * la;
   const int cnt = lb * lb - kb;
   const int S = cnt | 1;
-  const bool bwd = P.gY != nullptr;
+  constexpr bool bwd = FUSED;
   const int p = lane >> 2;
   if (bwd) {
     const T* src = static_cast<const T*>(P.gY) + p0 * K + kb;
@@ -169,30 +169,30 @@ __device__ __forceinline__ void fwd4_group(const Role<T>& ro, const Point<T>& pt
     T* dst = static_cast<T*>(P.Y) + p0 * K + kb;
     copy_out(st, S, dst, K, cnt, np, lane, aligned16(dst));
   }
-  if (P.dY != nullptr) {
+  if constexpr (STORE) {
     T* dst = static_cast<T*>(P.dY) + p0 * 3 * K + kb;
     copy_out(st + kQuadPoints * S, S, dst, K, cnt, 3 * np, lane, aligned16(dst));
   }
   __syncthreads();
 }
 
-// One compile-time group of degrees [LA, LB): sizes are constants, full
-// tiles go out through the unpredicated fixed-size copy.
-template <typename T, int MM, bool NORM, int LA, int LB>
+// One compile-time group of degrees [LA, LB).  FAST: a full 16-point tile of
+// a one-group plan with 16-byte aligned outputs, copied out with the
+// fixed-size unpredicated copy; otherwise the general copy.
+template <typename T, int MM, bool NORM, bool FUSED, bool STORE, bool FAST, int LA, int LB>
 __device__ __forceinline__ void fwd4_group_ct(const Role<T>& ro, const Point<T>& pt, int K, int64_t p0, int np,
                                               int lane, int lrow, const FwdParams& P, T* st, T* sg, T& acc) {
   constexpr int kb = LA * LA;
   constexpr int cnt = LB * LB - kb;
   constexpr int S = cnt | 1;
-  const bool bwd = P.gY != nullptr;
   const int p = lane >> 2;
-  if (bwd) {
+  if constexpr (FUSED) {
     const T* src = static_cast<const T*>(P.gY) + p0 * K + kb;
     copy_in(sg, S, src, K, cnt, np, lane, aligned16(src));
   }
   emit4_ct<T, MM, NORM, LA, LB>(ro, pt, st + lrow * S - kb);
   __syncthreads();
-  if (bwd) {
+  if constexpr (FUSED) {
     const T* gr = sg + p * S;
     const T* dr = st + lrow * S;
     T s0 = T(0), s1 = T(0);
@@ -204,36 +204,56 @@ __device__ __forceinline__ void fwd4_group_ct(const Role<T>& ro, const Point<T>&
     if constexpr (cnt % 2 == 1) s0 += gr[cnt - 1] * dr[cnt - 1];
     acc += s0 + s1;
   }
-  constexpr int W = Vec16<T>::n;
   T* ydst = static_cast<T*>(P.Y) + p0 * K + kb;
-  T* ddst = P.dY != nullptr ? static_cast<T*>(P.dY) + p0 * 3 * K + kb : nullptr;
-  if constexpr (S == cnt && kb == 0) {  // one group of degrees: contiguous tiles
-    const bool full = np == kQuadPoints && aligned16(ydst) && (ddst == nullptr || aligned16(ddst));
-    if (full) {
-      copy_out_full<T, kQuadPoints * cnt / W>(st, ydst, lane);
-      if (ddst != nullptr) copy_out_full<T, 3 * kQuadPoints * cnt / W>(st + kQuadPoints * S, ddst, lane);
-      __syncthreads();
-      return;
-    }
+  T* ddst = STORE ? static_cast<T*>(P.dY) + p0 * 3 * K + kb : nullptr;
+  if constexpr (FAST) {
+    static_assert(S == cnt && kb == 0, "fast path needs one contiguous group");
+    constexpr int W = Vec16<T>::n;
+    copy_out_full<T, kQuadPoints * cnt / W>(st, ydst, lane);
+    if constexpr (STORE) copy_out_full<T, 3 * kQuadPoints * cnt / W>(st + kQuadPoints * S, ddst, lane);
+  } else {
+    copy_out(st, S, ydst, K, cnt, np, lane, aligned16(ydst));
+    if constexpr (STORE) copy_out(st + kQuadPoints * S, S, ddst, K, cnt, 3 * np, lane, aligned16(ddst));
   }
-  copy_out(st, S, ydst, K, cnt, np, lane, aligned16(ydst));
-  if (ddst != nullptr) copy_out(st + kQuadPoints * S, S, ddst, K, cnt, 3 * np, lane, aligned16(ddst));
   __syncthreads();
 }
 
-template <typename T, int MM, bool NORM, int LT, int... Gs>
+template <typename T, int MM, bool NORM, bool FUSED, bool STORE, bool FAST, int LT, int... Gs>
 __device__ __forceinline__ void fwd4_groups_ct(std::integer_sequence<int, Gs...>, const Role<T>& ro,
                                                const Point<T>& pt, int K, int64_t p0, int np, int lane,
                                                int lrow, const FwdParams& P, T* st, T* sg, T& acc) {
   constexpr Plan PL = make_plan(LT, kQuadBudget<T>);
-  (fwd4_group_ct<T, MM, NORM, PL.lo[Gs], PL.hi[Gs]>(ro, pt, K, p0, np, lane, lrow, P, st, sg, acc), ...);
+  (fwd4_group_ct<T, MM, NORM, FUSED, STORE, FAST, PL.lo[Gs], PL.hi[Gs]>(ro, pt, K, p0, np, lane, lrow, P, st, sg,
+                                                                        acc),
+   ...);
+}
+
+// Whether a compile-time l_max has a single contiguous group (the fast
+// full-tile path).
+template <typename T, int LT>
+constexpr bool quad_has_fast() {
+  if constexpr (LT < 0) {
+    return false;
+  } else {
+    constexpr Plan PL = make_plan(LT, kQuadBudget<T>);
+    constexpr int K = (LT + 1) * (LT + 1);
+    return PL.ng == 1 && (K % 2 == 1);
+  }
 }
 
 // LT >= 0: l_max = LT known at compile time (MM = LT, degree loops unrolled);
-// LT < 0: l_max = P.L <= MM at run time.  Dynamic LDS: 64 rows of
-// stride(L) elements, plus 16 rows for the upstream-gradient tile when the
-// backward is fused.
-template <typename T, int MM, int LT, bool NORM>
+// LT < 0: l_max = P.L <= MM at run time.  FUSED: the backward is fused
+// (P.gY, P.gxyz); STORE: dY is written.  Dynamic LDS: 64 rows of stride(L)
+// elements, plus 16 rows for the upstream-gradient tile when FUSED.
+//
+// Full tiles of a one-group plan run a single straight path per tile: the
+// next tile's coordinates are loaded first and the tile's stores follow, so
+// the wait for that load leaves the stores in flight (loads and stores
+// retire in order on one counter).  A branch in the loop whose paths issue
+// different numbers of memory operations would turn that wait into a drain
+// of every store of the tile, so the ragged last tile and unaligned outputs
+// take a separate general path.
+template <typename T, int MM, int LT, bool NORM, bool FUSED, bool STORE>
 __global__ __launch_bounds__(kWave) void k_fwd4(FwdParams P) {
   constexpr int B = kQuadBudget<T>;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -250,40 +270,61 @@ __global__ __launch_bounds__(kWave) void k_fwd4(FwdParams P) {
   if (P.status != nullptr && blockIdx.x == 0) check_offsets(P, lane);
 
   const T* xyz = static_cast<const T*>(P.xyz);
-  // The coordinates of the block's next tile are loaded while the current
-  // tile is processed.
-  auto load_point = [&](int64_t tile, T& x, T& y, T& z) {
-    const int64_t i = tile * kQuadPoints + p;
-    x = y = z = T(0);
-    if (i < P.n) {
-      const T* q = xyz + i * 3;
-      x = q[0];
-      y = q[1];
-      z = q[2];
-    }
-  };
-  T nx, ny, nz;
-  load_point(blockIdx.x, nx, ny, nz);
-  for (int64_t tile = blockIdx.x; tile * kQuadPoints < P.n; tile += gridDim.x) {
+  auto tile_body = [&](int64_t tile, T x, T y, T z, auto fast_c) {
+    constexpr bool FAST = decltype(fast_c)::value;
     const int64_t p0 = tile * kQuadPoints;
-    const int np = static_cast<int>(P.n - p0 < kQuadPoints ? P.n - p0 : kQuadPoints);
-    const T x = nx, y = ny, z = nz;
-    load_point(tile + gridDim.x, nx, ny, nz);
+    const int np = FAST ? kQuadPoints : static_cast<int>(P.n - p0 < kQuadPoints ? P.n - p0 : kQuadPoints);
     const Point<T> pt = make_point<T, NORM>(x, y, z);
     const Role<T> ro = make_role<T, NORM>(r, pt);
     T acc = T(0);
     if constexpr (LT >= 0) {
       constexpr Plan PL = make_plan(LT, B);
-      fwd4_groups_ct<T, MM, NORM, LT>(std::make_integer_sequence<int, PL.ng>{}, ro, pt, K, p0, np, lane, lrow, P,
-                                      st, sg, acc);
+      fwd4_groups_ct<T, MM, NORM, FUSED, STORE, FAST, LT>(std::make_integer_sequence<int, PL.ng>{}, ro, pt, K,
+                                                          p0, np, lane, lrow, P, st, sg, acc);
     } else {
       for (int la = 0; la <= L;) {
         const int lb = group_end(la, L, B);
-        fwd4_group<T, MM, NORM, false>(ro, pt, la, lb, K, p0, np, lane, lrow, P, st, sg, acc);
+        fwd4_group<T, MM, NORM, false, FUSED, STORE>(ro, pt, la, lb, K, p0, np, lane, lrow, P, st, sg, acc);
         la = lb;
       }
     }
-    if (P.gY != nullptr && r > 0 && p < np) static_cast<T*>(P.gxyz)[(p0 + p) * 3 + (r - 1)] = acc;
+    if constexpr (FUSED) {
+      if (r > 0 && p < np) static_cast<T*>(P.gxyz)[(p0 + p) * 3 + (r - 1)] = acc;
+    }
+  };
+  auto load_point = [&](int64_t i, T& x, T& y, T& z) {
+    const T* q = xyz + i * 3;
+    x = q[0];
+    y = q[1];
+    z = q[2];
+  };
+
+  constexpr bool kFast = quad_has_fast<T, LT>();
+  const bool aligned = aligned16(P.Y) && (!STORE || aligned16(P.dY));
+  if (kFast && aligned) {
+    const int64_t nfull = P.n / kQuadPoints;
+    if (static_cast<int64_t>(blockIdx.x) < nfull) {
+      T nx, ny, nz;
+      load_point(blockIdx.x * kQuadPoints + p, nx, ny, nz);
+      for (int64_t tile = blockIdx.x; tile < nfull; tile += gridDim.x) {
+        const T x = nx, y = ny, z = nz;
+        // next full tile (clamped, so the load is unconditional)
+        const int64_t nt = tile + gridDim.x < nfull ? tile + gridDim.x : tile;
+        load_point(nt * kQuadPoints + p, nx, ny, nz);
+        tile_body(tile, x, y, z, std::integral_constant<bool, kFast>{});
+      }
+    }
+    if (P.n % kQuadPoints != 0 && nfull % gridDim.x == blockIdx.x) {
+      T x = T(0), y = T(0), z = T(0);
+      if (nfull * kQuadPoints + p < P.n) load_point(nfull * kQuadPoints + p, x, y, z);
+      tile_body(nfull, x, y, z, std::false_type{});
+    }
+  } else {
+    for (int64_t tile = blockIdx.x; tile * kQuadPoints < P.n; tile += gridDim.x) {
+      T x = T(0), y = T(0), z = T(0);
+      if (tile * kQuadPoints + p < P.n) load_point(tile * kQuadPoints + p, x, y, z);
+      tile_body(tile, x, y, z, std::false_type{});
+    }
   }
 }
 

@@ -1,7 +1,8 @@
 // Explicit kernel instantiations and lookup tables for one element type and
 // one kernel family.  Included by the sph_kernels_*.hip translation units with
-// SPH_T, SPH_SUFFIX and SPH_FAMILY defined (1 = forward kernels for one
-// normalisation SPH_NORM, 2 = backward and double backward).
+// SPH_T, SPH_SUFFIX and SPH_FAMILY defined: 1 = values-only forward and 3 =
+// forward with derivatives (mode SPH_MODE), both for one normalisation
+// SPH_NORM; 2 = backward and double backward.
 #include <utility>
 
 #include "sph_bwd.inl"
@@ -11,7 +12,6 @@
 
 #define SPH_CAT2(a, b) a##b
 #define SPH_CAT(a, b) SPH_CAT2(a, b)
-#define SPH_CAT3(a, b, c) SPH_CAT(SPH_CAT(a, b), c)
 
 namespace sph {
 namespace {
@@ -20,7 +20,7 @@ using T = SPH_T;
 using Buckets = std::make_integer_sequence<int, kNumBuckets>;
 bool in_range(int L) { return L >= 0 && L <= kMaxL; }
 
-#if SPH_FAMILY == 1
+#if SPH_FAMILY == 1 || SPH_FAMILY == 3
 constexpr bool kNorm = SPH_NORM != 0;
 // float32 specialises l_max <= 8 at compile time (degree loops unrolled,
 // coefficients as literals); everything else uses the run-time-degree
@@ -28,36 +28,40 @@ constexpr bool kNorm = SPH_NORM != 0;
 constexpr int kSpecMax = std::is_same_v<T, float> ? 8 : -1;
 constexpr int kSpecSlots = kSpecMax + 1 > 0 ? kSpecMax + 1 : 1;
 
+#if SPH_FAMILY == 1
+template <int MM, int LT>
+const void* kernel_ptr() {
+  return reinterpret_cast<const void*>(&k_fwd<T, MM, LT, kNorm>);
+}
+#else
+constexpr bool kFused = SPH_MODE != kDerivStore;
+constexpr bool kStore = SPH_MODE != kDerivFused;
+template <int MM, int LT>
+const void* kernel_ptr() {
+  return reinterpret_cast<const void*>(&k_fwd4<T, MM, LT, kNorm, kFused, kStore>);
+}
+#endif
+
 template <int... Ls>
-void fill_spec(const void** vals, const void** ders, std::integer_sequence<int, Ls...>) {
+void fill_spec(const void** out, std::integer_sequence<int, Ls...>) {
   if constexpr (kSpecMax >= 0) {
-    const void* v[] = {reinterpret_cast<const void*>(&k_fwd<T, Ls, Ls, kNorm>)...};
-    const void* d[] = {reinterpret_cast<const void*>(&k_fwd4<T, Ls, Ls, kNorm>)...};
-    for (size_t i = 0; i < sizeof...(Ls); ++i) {
-      vals[i] = v[i];
-      ders[i] = d[i];
-    }
+    const void* v[] = {kernel_ptr<Ls, Ls>()...};
+    for (size_t i = 0; i < sizeof...(Ls); ++i) out[i] = v[i];
   }
 }
 
 template <int... Is>
-void fill_buckets(const void** vals, const void** ders, std::integer_sequence<int, Is...>) {
-  const void* v[] = {reinterpret_cast<const void*>(&k_fwd<T, kBuckets[Is], -1, kNorm>)...};
-  const void* d[] = {reinterpret_cast<const void*>(&k_fwd4<T, kBuckets[Is], -1, kNorm>)...};
-  for (size_t i = 0; i < sizeof...(Is); ++i) {
-    vals[i] = v[i];
-    ders[i] = d[i];
-  }
+void fill_buckets(const void** out, std::integer_sequence<int, Is...>) {
+  const void* v[] = {kernel_ptr<kBuckets[Is], -1>()...};
+  for (size_t i = 0; i < sizeof...(Is); ++i) out[i] = v[i];
 }
 
 struct Tables {
-  const void* spec_vals[kSpecSlots] = {};
-  const void* spec_ders[kSpecSlots] = {};
-  const void* vals[kNumBuckets] = {};
-  const void* ders[kNumBuckets] = {};
+  const void* spec[kSpecSlots] = {};
+  const void* buckets[kNumBuckets] = {};
   Tables() {
-    if constexpr (kSpecMax >= 0) fill_spec(spec_vals, spec_ders, std::make_integer_sequence<int, kSpecSlots>{});
-    fill_buckets(vals, ders, Buckets{});
+    if constexpr (kSpecMax >= 0) fill_spec(spec, std::make_integer_sequence<int, kSpecSlots>{});
+    fill_buckets(buckets, Buckets{});
   }
 };
 #else
@@ -86,16 +90,16 @@ const Tables& tables() {
 }  // namespace
 
 #if SPH_FAMILY == 1
-KernelInfo SPH_CAT3(SPH_CAT(fwd_values_, SPH_SUFFIX), _n, SPH_NORM)(int L) {
+KernelInfo SPH_CAT(SPH_CAT(SPH_CAT(fwd_values_, SPH_SUFFIX), _n), SPH_NORM)(int L) {
   if (!in_range(L)) return KernelInfo{nullptr, 0, 0, 0};
-  const void* fn = L <= kSpecMax ? tables().spec_vals[L] : tables().vals[bucket_index(L)];
+  const void* fn = L <= kSpecMax ? tables().spec[L] : tables().buckets[bucket_index(L)];
   const size_t lds = sizeof(T) * kWave * static_cast<size_t>(plan_stride(L, kValueBudget<T>));
   return KernelInfo{fn, lds, lds, kWave};
 }
-
-KernelInfo SPH_CAT3(SPH_CAT(fwd_derivs_, SPH_SUFFIX), _n, SPH_NORM)(int L) {
+#elif SPH_FAMILY == 3
+KernelInfo SPH_CAT(SPH_CAT(SPH_CAT(SPH_CAT(SPH_CAT(fwd_derivs_, SPH_SUFFIX), _n), SPH_NORM), _m), SPH_MODE)(int L) {
   if (!in_range(L)) return KernelInfo{nullptr, 0, 0, 0};
-  const void* fn = L <= kSpecMax ? tables().spec_ders[L] : tables().ders[bucket_index(L)];
+  const void* fn = L <= kSpecMax ? tables().spec[L] : tables().buckets[bucket_index(L)];
   const size_t row = sizeof(T) * static_cast<size_t>(plan_stride(L, kQuadBudget<T>));
   return KernelInfo{fn, row * kWave, row * (kWave + kQuadPoints), kQuadPoints};
 }

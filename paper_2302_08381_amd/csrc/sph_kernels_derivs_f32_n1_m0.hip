@@ -1,0 +1,7 @@
+// forward kernels with derivatives (Y and dY), float, normalised harmonics
+#define SPH_T float
+#define SPH_SUFFIX f32
+#define SPH_FAMILY 3
+#define SPH_NORM 1
+#define SPH_MODE 0
+#include "sph_instances.inl"

@@ -58,16 +58,26 @@ struct KernelInfo {
 // Per element type (suffix f32 / f64) and normalisation; fn == nullptr when
 // the arguments are out of range.
 //   values:      Y only (one lane per point, 64-point tiles)
-//   derivatives: Y and dY and/or the fused backward (four lanes per point,
-//                16-point tiles)
+//   derivatives: four lanes per point, 16-point tiles; mode
+//                kDerivStore (Y and dY), kDerivFusedStore (Y, dY and the
+//                fused backward), kDerivFused (Y and the fused backward)
+enum DerivMode { kDerivStore = 0, kDerivFusedStore = 1, kDerivFused = 2, kNumDerivModes = 3 };
 KernelInfo fwd_values_f32_n0(int L);
 KernelInfo fwd_values_f32_n1(int L);
 KernelInfo fwd_values_f64_n0(int L);
 KernelInfo fwd_values_f64_n1(int L);
-KernelInfo fwd_derivs_f32_n0(int L);
-KernelInfo fwd_derivs_f32_n1(int L);
-KernelInfo fwd_derivs_f64_n0(int L);
-KernelInfo fwd_derivs_f64_n1(int L);
+KernelInfo fwd_derivs_f32_n0_m0(int L);
+KernelInfo fwd_derivs_f32_n0_m1(int L);
+KernelInfo fwd_derivs_f32_n0_m2(int L);
+KernelInfo fwd_derivs_f32_n1_m0(int L);
+KernelInfo fwd_derivs_f32_n1_m1(int L);
+KernelInfo fwd_derivs_f32_n1_m2(int L);
+KernelInfo fwd_derivs_f64_n0_m0(int L);
+KernelInfo fwd_derivs_f64_n0_m1(int L);
+KernelInfo fwd_derivs_f64_n0_m2(int L);
+KernelInfo fwd_derivs_f64_n1_m0(int L);
+KernelInfo fwd_derivs_f64_n1_m1(int L);
+KernelInfo fwd_derivs_f64_n1_m2(int L);
 KernelInfo bwd_info_f32(int L);
 KernelInfo bwd_info_f64(int L);
 KernelInfo dbwd_info_f32(int L, int normalize);
