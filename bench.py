@@ -100,12 +100,94 @@ def accuracy(xyz, Y, dY, gY, gx, rows: int = 2048):
             "grad_xyz_max_scaled_err": mb, "tolerance": 1e-5}
 
 
+def _time(fn, reps: int, warm: int = 3) -> float:
+    """Mean seconds per call of fn() on the current stream (HIP events)."""
+    import torch
+    for _ in range(warm):
+        fn()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / reps
+
+
+def extras(dev):
+    """Secondary measurements of the other parts of the path (not the headline)."""
+    import numpy as np
+    import torch
+
+    import paper_2302_08381_amd as sph
+    from workloads import SEEDS, csr_environments, shell_points, standard_normal, standard_normal_points
+    out = {}
+    # float64, same workload as the headline
+    K = (L_MAX + 1) ** 2
+    x64 = torch.as_tensor(standard_normal_points(N_POINTS, SEEDS["plain_gpu"]), dtype=torch.float64).to(dev)
+    g64 = torch.as_tensor(standard_normal((N_POINTS, K), SEEDS["plain_gpu_grad"]), dtype=torch.float64).to(dev)
+    Y = torch.empty((N_POINTS, K), dtype=torch.float64, device=dev)
+    dY = torch.empty((N_POINTS, 3, K), dtype=torch.float64, device=dev)
+    gx = torch.empty((N_POINTS, 3), dtype=torch.float64, device=dev)
+    tf = _time(lambda: sph.sph_compute_with_gradients(x64, L_MAX, NORMALIZE, Y=Y, dY=dY), 20)
+    tb = _time(lambda: sph.sph_backward(dY, g64, L_MAX, grad_xyz=gx), 20)
+    b = N_POINTS * 8 * (3 + 4 * K)
+    out["f64_l8"] = {"forward_s": tf, "backward_s": tb, "points_per_s_fwd_bwd": N_POINTS / (tf + tb),
+                     "forward_GB_per_s": b / tf / 1e9, "backward_GB_per_s": b / tb / 1e9}
+    del x64, g64, Y, dY, gx
+    # values only, float32
+    x32 = torch.as_tensor(standard_normal_points(N_POINTS, SEEDS["plain_gpu"]), dtype=torch.float32).to(dev)
+    Yv = torch.empty((N_POINTS, K), dtype=torch.float32, device=dev)
+    tv = _time(lambda: sph.sph_compute(x32, L_MAX, NORMALIZE, Y=Yv), 30)
+    out["values_only_l8_f32"] = {"s": tv, "points_per_s": N_POINTS / tv,
+                                 "GB_per_s": N_POINTS * 4 * (3 + K) / tv / 1e9}
+    del x32, Yv
+    # double backward: 4e6 points in the ball 0.5..5, l_max = 6, float32, normalised
+    n3, L3 = 4_000_000, 6
+    K3 = (L3 + 1) ** 2
+    xb = torch.as_tensor(shell_points(n3, 0.5, 5.0, SEEDS["diff"]), dtype=torch.float32).to(dev)
+    gYb = torch.as_tensor(standard_normal((n3, K3), 31), dtype=torch.float32).to(dev)
+    vb = torch.as_tensor(standard_normal((n3, 3), 32), dtype=torch.float32).to(dev)
+    td = _time(lambda: sph.sph_double_backward(xb, gYb, vb, L3, True), 10)
+    out["double_backward_l6_f32_4M"] = {"s": td, "points_per_s": n3 / td,
+                                        "GB_per_s": n3 * 4 * (3 + K3 + 3 + K3 + 3) / td / 1e9}
+    del xb, gYb, vb
+    # batched: 20 000 environments, fused forward + backward with dY, per l_max
+    pts, offs = csr_environments(20_000, 8, 128, 0.5, 5.0, SEEDS["batched"])
+    nb = int(offs[-1])
+    xc = torch.as_tensor(pts, dtype=torch.float32).to(dev)
+    oc = torch.as_tensor(offs, device=dev)
+    bat = {}
+    for Lb in (3, 6, 8, 12):
+        Kb = (Lb + 1) ** 2
+        gYc = torch.as_tensor(standard_normal((nb, Kb), 1000 + Lb), dtype=torch.float32).to(dev)
+        o = {"Y": torch.empty((nb, Kb), device=dev), "dY": torch.empty((nb, 3, Kb), device=dev),
+             "grad_xyz": torch.empty((nb, 3), device=dev)}
+        tbat = _time(lambda: sph.sph_batched_compute(xc, oc, Lb, True, store_dY=True, grad_Y=gYc, out=o), 20)
+        Yp = torch.empty((nb, Kb), device=dev)
+        dYp = torch.empty((nb, 3, Kb), device=dev)
+        gxp = torch.empty((nb, 3), device=dev)
+
+        def plain():
+            sph.sph_compute_with_gradients(xc, Lb, True, Y=Yp, dY=dYp)
+            sph.sph_backward(dYp, gYc, Lb, grad_xyz=gxp)
+        tpl = _time(plain, 20)
+        bat[str(Lb)] = {"batched_fused_s": tbat, "plain_fwd_bwd_s": tpl, "points": nb,
+                        "batched_points_per_s": nb / tbat, "plain_points_per_s": nb / tpl,
+                        "config": sph.sph_batched_get_config(Lb, True, torch.float32, True, True)}
+    out["batched_20k_envs_f32"] = bat
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the secondary measurements")
     ap.add_argument("--profile", action="store_true",
                     help="only run warmup + steps (and a 1 GiB reference copy), for rocprofv3")
     args = ap.parse_args()
@@ -225,6 +307,8 @@ def main():
         "accuracy": acc,
         "kernel_sources": kernel_hash(),
     }
+    if not args.no_extras:
+        out["extra"] = extras(dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

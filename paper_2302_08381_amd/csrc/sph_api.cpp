@@ -134,32 +134,12 @@ hipError_t launch(const void* fn, unsigned grid, unsigned block, size_t lds, voi
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Grid of a plain forward call: as many blocks as can be resident at once
-// (occupancy from the runtime for this kernel and LDS size), each looping
-// over tiles; never more blocks than tiles.
-std::mutex g_occ_mu;
-std::map<std::tuple<int, const void*, size_t>, int> g_occ;
-
-int64_t resident_grid(const void* fn, size_t lds, int64_t tiles) {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
-  int per_cu = 0;
-  {
-    std::lock_guard<std::mutex> lk(g_occ_mu);
-    auto key = std::make_tuple(dev, fn, lds);
-    auto it = g_occ.find(key);
-    if (it != g_occ.end()) {
-      per_cu = it->second;
-    } else {
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, sph::kBlock, lds) != hipSuccess ||
-          per_cu <= 0)
-        per_cu = 4;
-      (void)hipGetLastError();
-      g_occ[key] = per_cu;
-    }
-  }
-  return std::max<int64_t>(1, std::min<int64_t>(tiles, int64_t(num_cus()) * per_cu));
-}
+// Grid of a plain forward call: one tile per block.  Blocks that each write
+// one tile and exit keep the chip's concurrent stores on a compact, advancing
+// address range; a resident grid of blocks looping over tiles spreads them
+// over as many separate streams as there are blocks and writes measurably
+// slower.  Beyond 2^31 - 1 tiles the kernels loop over the rest.
+int64_t plain_grid(int64_t tiles) { return std::max<int64_t>(1, std::min<int64_t>(tiles, 0x7fffffff)); }
 
 // ------------------------------------------------------------ batched path
 struct BatchKey {
@@ -253,11 +233,11 @@ Choice autotune(const sph::KernelInfo& ki, size_t lds, sph::FwdParams params, hi
   for (int bpc : kBpcCandidates) {
     const unsigned grid = batched_grid(ki, params.n, bpc);
     sph::FwdParams p = params;
-    if (launch(ki.fn, grid, sph::kBlock, lds, &p, s) != hipSuccess) continue;  // warm-up
+    if (launch(ki.fn, grid, ki.block, lds, &p, s) != hipSuccess) continue;  // warm-up
     (void)hipEventRecord(e0, s);
     constexpr int reps = 3;
     bool okr = true;
-    for (int r = 0; r < reps && okr; ++r) okr = launch(ki.fn, grid, sph::kBlock, lds, &p, s) == hipSuccess;
+    for (int r = 0; r < reps && okr; ++r) okr = launch(ki.fn, grid, ki.block, lds, &p, s) == hipSuccess;
     (void)hipEventRecord(e1, s);
     if (!okr || hipEventSynchronize(e1) != hipSuccess) continue;
     float ms = 0;
@@ -316,8 +296,8 @@ int32_t sph_compute_with_gradients(const void* xyz, int64_t n, int32_t l_max, in
   hipError_t e = ensure_lds(ki.fn, ki.lds_bytes);
   if (e != hipSuccess) return device_fail(e, "hipFuncSetAttribute");
   sph::FwdParams p{xyz, n, l_max, Y, dY, nullptr, nullptr, nullptr, 0, nullptr};
-  const int64_t grid = resident_grid(ki.fn, ki.lds_bytes, ceil_div(n, ki.tile_points));
-  e = launch(ki.fn, static_cast<unsigned>(grid), sph::kBlock, ki.lds_bytes, &p,
+  const int64_t grid = plain_grid(ceil_div(n, ki.tile_points));
+  e = launch(ki.fn, static_cast<unsigned>(grid), ki.block, ki.lds_bytes, &p,
              static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return device_fail(e, "forward launch");
   return ok();
@@ -344,9 +324,9 @@ int32_t sph_backward(const void* dY, const void* grad_Y, int64_t n, int32_t l_ma
   const sph::KernelInfo ki = bwd_info(dtype, l_max);
   if (ki.fn == nullptr) return fail(SPH_ERR_INVALID, "no kernel for these arguments");
   sph::BwdParams p{dY, grad_Y, n, static_cast<int32_t>(K), grad_xyz};
-  const int64_t grid = ceil_div(n, sph::kBwdPointsPerBlock);
+  const int64_t grid = ceil_div(n, ki.tile_points);
   if (grid > 0x7fffffff) return fail(SPH_ERR_INVALID, "n too large for one launch");
-  hipError_t e = launch(ki.fn, static_cast<unsigned>(grid), sph::kBlock, 0, &p, static_cast<hipStream_t>(stream));
+  hipError_t e = launch(ki.fn, static_cast<unsigned>(grid), ki.block, 0, &p, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return device_fail(e, "backward launch");
   return ok();
 }
@@ -373,9 +353,9 @@ int32_t sph_double_backward(const void* xyz, const void* grad_Y, const void* v, 
   hipError_t e = ensure_lds(ki.fn, ki.lds_bytes);
   if (e != hipSuccess) return device_fail(e, "hipFuncSetAttribute");
   sph::DbwdParams p{xyz, grad_Y, v, n, l_max, grad_grad_Y, grad_xyz2};
-  const int64_t grid = ceil_div(n, sph::kPointsPerBlock);
+  const int64_t grid = ceil_div(n, ki.tile_points);
   if (grid > 0x7fffffff) return fail(SPH_ERR_INVALID, "n too large for one launch");
-  e = launch(ki.fn, static_cast<unsigned>(grid), sph::kBlock, ki.lds_bytes, &p,
+  e = launch(ki.fn, static_cast<unsigned>(grid), ki.block, ki.lds_bytes, &p,
              static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return device_fail(e, "double backward launch");
   return ok();
@@ -461,7 +441,7 @@ int32_t sph_batched_compute(const void* xyz, const int64_t* offsets, int64_t n_e
   const unsigned grid = batched_grid(ki, n_points, ch.blocks_per_cu);
 
   if (!g_use_graph || capturing) {
-    e = launch(ki.fn, grid, sph::kBlock, lds, &p, s);
+    e = launch(ki.fn, grid, ki.block, lds, &p, s);
     if (e != hipSuccess) return device_fail(e, "batched launch");
     return ok();
   }
@@ -472,7 +452,7 @@ int32_t sph_batched_compute(const void* xyz, const int64_t* offsets, int64_t n_e
   GraphEntry& g = g_graphs[gkey];
   void* args[] = {&p};
   hipKernelNodeParams np{};
-  np.blockDim = dim3(sph::kBlock);
+  np.blockDim = dim3(ki.block);
   np.gridDim = dim3(grid);
   np.func = const_cast<void*>(ki.fn);
   np.kernelParams = args;

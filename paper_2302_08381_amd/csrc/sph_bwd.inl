@@ -1,12 +1,15 @@
 // Backward (vector-Jacobian product) with stored derivatives:
 //   gxyz[i,a] = sum_k gY[i,k] dY[i,a,k]
 // A streaming contraction (no MFMA: one short dot product per point and
-// axis).  A block of 64 lanes takes 16 points; the gY rows and the 48 dY rows
-// of those points are copied into LDS with coalesced (16-byte when possible)
-// loads, in chunks of at most KC columns.  Lane (p, q) then sums columns
-// k = q (mod 4) of point p for the three axes, and the four partial sums are
-// combined with two lane exchanges.  The summation order is fixed, so the
-// result is deterministic.
+// axis).  A block of 128 threads takes 32 points (for odd K the block's share
+// of gY and dY is then a whole number of 128-byte lines).  The gY rows and the
+// 96 dY rows of those points are copied into LDS with coalesced (16-byte when
+// possible) loads in chunks of at most KC columns, kBwdBatch loads in flight
+// per thread: deep enough that one round trip covers a chunk, since at the
+// occupancy the LDS tile allows the kernel is bound by read latency.  Thread
+// (p, q) then sums columns k = q (mod 4) of point p for the three axes, and
+// the four partial sums are combined with two lane exchanges.  The summation
+// order is fixed, so the result is deterministic.
 #pragma once
 
 #include "sph_device.hpp"
@@ -18,10 +21,11 @@ template <typename T>
 inline constexpr int kBwdChunk = 84;
 template <>
 inline constexpr int kBwdChunk<double> = 42;
+constexpr int kBwdBatch = 16;
 
 template <typename T>
-__global__ __launch_bounds__(kWave) void k_bwd(BwdParams P) {
-  constexpr int PP = kBwdPointsPerBlock;  // 16 points per block
+__global__ __launch_bounds__(kBwdThreads) void k_bwd(BwdParams P) {
+  constexpr int PP = kBwdPointsPerBlock;  // 32 points per block
   constexpr int KC = kBwdChunk<T>;
   constexpr int SC = KC | 1;
   __shared__ __align__(16) T sg[PP * SC];
@@ -40,8 +44,8 @@ __global__ __launch_bounds__(kWave) void k_bwd(BwdParams P) {
   for (int kc0 = 0; kc0 < K; kc0 += KC) {
     const int cnt = (K - kc0) < KC ? (K - kc0) : KC;
     const int S = cnt | 1;
-    copy_in(sg, S, gY + kc0, K, cnt, np, lane, aligned16(gY + kc0));
-    copy_in(sd, S, dY + kc0, K, cnt, 3 * np, lane, aligned16(dY + kc0));
+    copy_in<kBwdThreads, kBwdBatch>(sg, S, gY + kc0, K, cnt, np, lane, aligned16(gY + kc0));
+    copy_in<kBwdThreads, kBwdBatch>(sd, S, dY + kc0, K, cnt, 3 * np, lane, aligned16(dY + kc0));
     __syncthreads();
     if (pl < np) {
       const T* g = sg + pl * S;

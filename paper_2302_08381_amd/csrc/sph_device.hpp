@@ -283,13 +283,14 @@ __device__ __forceinline__ Point<T> make_point(T x, T y, T z) {
 // ------------------------------------------------------------ LDS <-> global
 // Copies between an LDS tile (rows of stride S) and global rows (stride
 // gstride): for row p < rows and j < cnt, dst[p * gstride + j] <-> st[p * S + j].
-// With gstride == cnt == S (one contiguous block) and a 16-byte aligned
-// global pointer the copy uses 16-byte accesses.  Each lane keeps kBatch
-// accesses in flight before it waits, so LDS and memory latency is paid once
-// per batch rather than once per element.
+// NT threads of the block take part (lane = thread index < NT).  With
+// gstride == cnt == S (one contiguous block) and a 16-byte aligned global
+// pointer the copy uses 16-byte accesses.  Each lane keeps NB accesses in
+// flight before it waits, so LDS and memory latency is paid once per batch
+// rather than once per element.
 constexpr int kBatch = 4;
 
-template <typename T>
+template <int NT = kWave, int NB = kBatch, typename T>
 __device__ __forceinline__ void copy_out(const T* __restrict__ st, int S, T* __restrict__ dst,
                                          int gstride, int cnt, int rows, int lane, bool vec) {
   const int total = rows * cnt;
@@ -299,29 +300,29 @@ __device__ __forceinline__ void copy_out(const T* __restrict__ st, int S, T* __r
     const int nv = total / W;
     const V* sv = reinterpret_cast<const V*>(st);
     V* dv = reinterpret_cast<V*>(dst);
-    for (int i0 = lane; i0 < nv; i0 += kWave * kBatch) {
-      V v[kBatch];
+    for (int i0 = lane; i0 < nv; i0 += NT * NB) {
+      V v[NB];
 #pragma unroll
-      for (int u = 0; u < kBatch; ++u)
-        if (i0 + u * kWave < nv) v[u] = sv[i0 + u * kWave];
+      for (int u = 0; u < NB; ++u)
+        if (i0 + u * NT < nv) v[u] = sv[i0 + u * NT];
 #pragma unroll
-      for (int u = 0; u < kBatch; ++u)
-        if (i0 + u * kWave < nv) __builtin_nontemporal_store(v[u], dv + i0 + u * kWave);
+      for (int u = 0; u < NB; ++u)
+        if (i0 + u * NT < nv) __builtin_nontemporal_store(v[u], dv + i0 + u * NT);
     }
-    for (int j = nv * W + lane; j < total; j += kWave) __builtin_nontemporal_store(st[j], dst + j);
+    for (int j = nv * W + lane; j < total; j += NT) __builtin_nontemporal_store(st[j], dst + j);
     return;
   }
   int p = lane / cnt;
   int k = lane - p * cnt;
-  const int qs = kWave / cnt;
-  const int rs = kWave - qs * cnt;
-  for (int j0 = lane; j0 < total; j0 += kWave * kBatch) {
-    T v[kBatch];
-    int off[kBatch];
+  const int qs = NT / cnt;
+  const int rs = NT - qs * cnt;
+  for (int j0 = lane; j0 < total; j0 += NT * NB) {
+    T v[NB];
+    int off[NB];
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
+    for (int u = 0; u < NB; ++u) {
       off[u] = p * gstride + k;
-      if (j0 + u * kWave < total) v[u] = st[p * S + k];
+      if (j0 + u * NT < total) v[u] = st[p * S + k];
       p += qs;
       k += rs;
       if (k >= cnt) {
@@ -330,12 +331,12 @@ __device__ __forceinline__ void copy_out(const T* __restrict__ st, int S, T* __r
       }
     }
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u)
-      if (j0 + u * kWave < total) __builtin_nontemporal_store(v[u], dst + off[u]);
+    for (int u = 0; u < NB; ++u)
+      if (j0 + u * NT < total) dst[off[u]] = v[u];  // partial lines: let L2 merge them
   }
 }
 
-template <typename T>
+template <int NT = kWave, int NB = kBatch, typename T>
 __device__ __forceinline__ void copy_in(T* __restrict__ st, int S, const T* __restrict__ src,
                                         int gstride, int cnt, int rows, int lane, bool vec) {
   const int total = rows * cnt;
@@ -345,29 +346,29 @@ __device__ __forceinline__ void copy_in(T* __restrict__ st, int S, const T* __re
     const int nv = total / W;
     V* sv = reinterpret_cast<V*>(st);
     const V* dv = reinterpret_cast<const V*>(src);
-    for (int i0 = lane; i0 < nv; i0 += kWave * kBatch) {
-      V v[kBatch];
+    for (int i0 = lane; i0 < nv; i0 += NT * NB) {
+      V v[NB];
 #pragma unroll
-      for (int u = 0; u < kBatch; ++u)
-        if (i0 + u * kWave < nv) v[u] = __builtin_nontemporal_load(dv + i0 + u * kWave);
+      for (int u = 0; u < NB; ++u)
+        if (i0 + u * NT < nv) v[u] = __builtin_nontemporal_load(dv + i0 + u * NT);
 #pragma unroll
-      for (int u = 0; u < kBatch; ++u)
-        if (i0 + u * kWave < nv) sv[i0 + u * kWave] = v[u];
+      for (int u = 0; u < NB; ++u)
+        if (i0 + u * NT < nv) sv[i0 + u * NT] = v[u];
     }
-    for (int j = nv * W + lane; j < total; j += kWave) st[j] = __builtin_nontemporal_load(src + j);
+    for (int j = nv * W + lane; j < total; j += NT) st[j] = __builtin_nontemporal_load(src + j);
     return;
   }
   int p = lane / cnt;
   int k = lane - p * cnt;
-  const int qs = kWave / cnt;
-  const int rs = kWave - qs * cnt;
-  for (int j0 = lane; j0 < total; j0 += kWave * kBatch) {
-    T v[kBatch];
-    int off[kBatch];
+  const int qs = NT / cnt;
+  const int rs = NT - qs * cnt;
+  for (int j0 = lane; j0 < total; j0 += NT * NB) {
+    T v[NB];
+    int off[NB];
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
+    for (int u = 0; u < NB; ++u) {
       off[u] = p * S + k;
-      if (j0 + u * kWave < total) v[u] = __builtin_nontemporal_load(src + (p * gstride + k));
+      if (j0 + u * NT < total) v[u] = __builtin_nontemporal_load(src + (p * gstride + k));
       p += qs;
       k += rs;
       if (k >= cnt) {
@@ -376,35 +377,35 @@ __device__ __forceinline__ void copy_in(T* __restrict__ st, int S, const T* __re
       }
     }
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u)
-      if (j0 + u * kWave < total) st[off[u]] = v[u];
+    for (int u = 0; u < NB; ++u)
+      if (j0 + u * NT < total) st[off[u]] = v[u];
   }
 }
 
 // Full-tile contiguous copy with compile-time size: NV 16-byte vectors from
-// LDS to global, kBatchFull in flight per lane, no predication except on the
-// last, partial sweep.
+// LDS to global by NT threads, kBatchFull in flight per lane, no predication
+// except on the last, partial sweep.
 constexpr int kBatchFull = 8;
 
-template <typename T, int NV>
+template <typename T, int NV, int NT = kWave>
 __device__ __forceinline__ void copy_out_full(const T* __restrict__ st, T* __restrict__ dst, int lane) {
   using V = typename Vec16<T>::type;
   const V* sv = reinterpret_cast<const V*>(st);
   V* dv = reinterpret_cast<V*>(dst);
-  constexpr int kSweeps = (NV + kWave - 1) / kWave;
+  constexpr int kSweeps = (NV + NT - 1) / NT;
 #pragma unroll
   for (int s0 = 0; s0 < kSweeps; s0 += kBatchFull) {
     V v[kBatchFull];
 #pragma unroll
     for (int u = 0; u < kBatchFull; ++u) {
       const int sw = s0 + u;
-      if (sw < kSweeps && (sw < NV / kWave || lane + sw * kWave < NV)) v[u] = sv[lane + sw * kWave];
+      if (sw < kSweeps && (sw < NV / NT || lane + sw * NT < NV)) v[u] = sv[lane + sw * NT];
     }
 #pragma unroll
     for (int u = 0; u < kBatchFull; ++u) {
       const int sw = s0 + u;
-      if (sw < kSweeps && (sw < NV / kWave || lane + sw * kWave < NV))
-        __builtin_nontemporal_store(v[u], dv + lane + sw * kWave);
+      if (sw < kSweeps && (sw < NV / NT || lane + sw * NT < NV))
+        __builtin_nontemporal_store(v[u], dv + lane + sw * NT);
     }
   }
 }

@@ -1,9 +1,10 @@
 // Forward with derivatives, four lanes per point.
 //
-// A wave takes 16 points; lane 4p + r of the wave evaluates point p and emits
-// component r of it: r = 0 the values, r = 1, 2, 3 the d/dx, d/dy, d/dz
-// derivatives.  Every lane runs the same instructions (the four components
-// differ only in per-lane weights, so nothing diverges):
+// A block of two waves takes a tile of 32 points; thread 4p + r evaluates
+// point p of the tile and emits component r of it: r = 0 the values, r = 1, 2,
+// 3 the d/dx, d/dy, d/dz derivatives.  Every lane runs the same instructions
+// (the four components differ only in per-lane weights, so nothing
+// diverges):
 //
 //   value(+m) = A c_m + B P+ ,  value(-m) = A s_m + B P-
 //   A = w_q Qt_l^m + w_t Tm + w_c Cm        (Tm = gxy Qt_{l-1}^{m+1}, Cm = gz Qt_{l-1}^m)
@@ -16,11 +17,16 @@
 // rule (d_a Yt(u) - l u_a Yt(u)) / r folds into A -> (A - l u_a Qt) / r and
 // B -> B / r.
 //
-// The LDS tile is laid out exactly as the global arrays: 16 value rows
-// (the points' Y rows) followed by 48 derivative rows (dY[p][a]); with one
+// The LDS tile is laid out exactly as the global arrays: 32 value rows
+// (the points' Y rows) followed by 96 derivative rows (dY[p][a]); with one
 // group of degrees both blocks are contiguous in global memory and are
-// copied out with 16-byte stores.  The fused backward (batched entry) adds
-// sum_k gY[p,k] dY[p,a,k] in lane 4p + a + 1, which then owns grad_xyz[p,a].
+// copied out with 16-byte stores.  A tile of 32 points makes each block's
+// share of Y and dY a whole number of 128-byte lines for every odd K (32 K
+// and 96 K floats), so no cache line is written by two blocks; with 16-point
+// tiles every other block boundary splits a line, and such partial lines
+// cost write bandwidth.  The fused backward (batched entry) adds
+// sum_k gY[p,k] dY[p,a,k] in thread 4p + a + 1, which then owns
+// grad_xyz[p,a].
 #pragma once
 
 #include "sph_device.hpp"
@@ -29,7 +35,9 @@
 
 namespace sph {
 
-constexpr int kQuadPoints = 16;
+constexpr int kQuadWaves = 2;                       // waves per block
+constexpr int kQuadPoints = 16 * kQuadWaves;        // points per tile (one block)
+constexpr int kQuadThreads = kWave * kQuadWaves;    // threads per block, 4 per point
 
 // Per-point LDS budget (elements of one component of one group of degrees).
 template <typename T>
@@ -123,16 +131,72 @@ __device__ __forceinline__ void emit4(const Role<T>& ro, const Point<T>& pt, int
   }
 }
 
-// Degrees [LA, LB) known at compile time: the degree loop unrolls fully and
-// every coefficient is a literal.
+// The lane's terms of order m that do not depend on the degree: c_m, s_m and
+// the product-rule factors m w_b P+(m), m w_b P-(m) (m <= MM, compile-time).
+template <typename T, int MM>
+struct MTerms {
+  T c[MM + 1], s[MM + 1], bp[MM + 1], bm[MM + 1];
+};
+
+template <typename T, int MM>
+__device__ __forceinline__ void make_mterms(const Role<T>& ro, const Point<T>& pt, MTerms<T, MM>& t) {
+  t.c[0] = T(1);
+  t.s[0] = T(0);
+  t.bp[0] = T(0);
+  t.bm[0] = T(0);
+#pragma unroll
+  for (int m = 1; m <= MM; ++m) {
+    const T cp = t.c[m - 1], sp = t.s[m - 1];
+    t.s[m] = pt.ex * sp + pt.ey * cp;
+    t.c[m] = pt.ex * cp - pt.ey * sp;
+    const T w = T(m) * ro.wb;
+    t.bp[m] = w * (cp * ro.a1 + sp * ro.a2);
+    t.bm[m] = w * (sp * ro.a1 - cp * ro.a2);
+  }
+}
+
+// emit4_row with the m terms tabulated and the weights pre-scaled:
+//   A = q ql + wts gxy Qt_{l-1}^{m+1} + wcs gz Qt_{l-1}^m,
+//   ql = (w_q - l u_a) s,  wts = w_t s,  wcs = w_c s   (s = 1/r or 1),
+// the same A as emit4_row (the chain-rule correction folded into ql), and
+//   value(+m) = A c_m + q bp_m,  value(-m) = A s_m + q bm_m.
+template <typename T, int MM>
+__device__ __forceinline__ void emit4_row_tab(int l, T ql, T wts, T wcs, const MTerms<T, MM>& t,
+                                              const T (&prev)[MM + 3], const T (&cur)[MM + 3], T* row) {
+  const CoefTable<T>& C = coef<T>();
+  constexpr T kIS2 = T(kInvSqrt2d);
+  const int k0 = l * l + l;
+#pragma unroll
+  for (int m = 0; m <= MM; ++m) {
+    if (m > l) continue;  // no early exit: keeps the loop fully unrolled
+    const T q = cur[m];
+    T A = q * ql;
+    if (m <= l - 2) A += (C.gxy[l][m] * prev[m + 1]) * wts;
+    if (m <= l - 1) A += (C.gz[l][m] * prev[m]) * wcs;
+    if (m == 0) {
+      row[k0] = A * kIS2;
+    } else {
+      row[k0 + m] = A * t.c[m] + q * t.bp[m];
+      row[k0 - m] = A * t.s[m] + q * t.bm[m];
+    }
+  }
+}
+
+// Degrees [LA, LB) known at compile time: the degree loop unrolls fully,
+// every coefficient is a literal and the terms of order m are computed once.
 template <typename T, int MM, bool NORM, int LA, int LB>
 __device__ __forceinline__ void emit4_ct(const Role<T>& ro, const Point<T>& pt, T* row) {
   T prev[MM + 3], cur[MM + 3];
+  MTerms<T, MM> t;
+  make_mterms<T, MM>(ro, pt, t);
+  const T wqs = ro.wq * ro.sc, lus = ro.lu * ro.sc;
+  const T wts = ro.wt * ro.sc, wcs = ro.wc * ro.sc;
   if constexpr (LA >= 1) q_row<T, MM>(LA - 1, pt.ez, pt.rxy2, prev);
 #pragma unroll
   for (int l = LA; l < LB; ++l) {
     q_row<T, MM>(l, pt.ez, pt.rxy2, cur);
-    emit4_row<T, MM, NORM>(l, ro, pt, prev, cur, row);
+    const T ql = NORM ? wqs - T(l) * lus : wqs;
+    emit4_row_tab<T, MM>(l, ql, wts, wcs, t, prev, cur, row);
     copy_row<T, MM>(l, cur, prev);
   }
 }
@@ -148,7 +212,7 @@ __device__ __forceinline__ void fwd4_group(const Role<T>& ro, const Point<T>& pt
   const int p = lane >> 2;
   if (bwd) {
     const T* src = static_cast<const T*>(P.gY) + p0 * K + kb;
-    copy_in(sg, S, src, K, cnt, np, lane, aligned16(src));
+    copy_in<kQuadThreads>(sg, S, src, K, cnt, np, lane, aligned16(src));
   }
   emit4<T, MM, NORM, UNROLL>(ro, pt, la, lb, st + lrow * S - kb);
   __syncthreads();
@@ -167,11 +231,11 @@ __device__ __forceinline__ void fwd4_group(const Role<T>& ro, const Point<T>& pt
   }
   {
     T* dst = static_cast<T*>(P.Y) + p0 * K + kb;
-    copy_out(st, S, dst, K, cnt, np, lane, aligned16(dst));
+    copy_out<kQuadThreads>(st, S, dst, K, cnt, np, lane, aligned16(dst));
   }
   if constexpr (STORE) {
     T* dst = static_cast<T*>(P.dY) + p0 * 3 * K + kb;
-    copy_out(st + kQuadPoints * S, S, dst, K, cnt, 3 * np, lane, aligned16(dst));
+    copy_out<kQuadThreads>(st + kQuadPoints * S, S, dst, K, cnt, 3 * np, lane, aligned16(dst));
   }
   __syncthreads();
 }
@@ -188,7 +252,7 @@ __device__ __forceinline__ void fwd4_group_ct(const Role<T>& ro, const Point<T>&
   const int p = lane >> 2;
   if constexpr (FUSED) {
     const T* src = static_cast<const T*>(P.gY) + p0 * K + kb;
-    copy_in(sg, S, src, K, cnt, np, lane, aligned16(src));
+    copy_in<kQuadThreads>(sg, S, src, K, cnt, np, lane, aligned16(src));
   }
   emit4_ct<T, MM, NORM, LA, LB>(ro, pt, st + lrow * S - kb);
   __syncthreads();
@@ -209,11 +273,13 @@ __device__ __forceinline__ void fwd4_group_ct(const Role<T>& ro, const Point<T>&
   if constexpr (FAST) {
     static_assert(S == cnt && kb == 0, "fast path needs one contiguous group");
     constexpr int W = Vec16<T>::n;
-    copy_out_full<T, kQuadPoints * cnt / W>(st, ydst, lane);
-    if constexpr (STORE) copy_out_full<T, 3 * kQuadPoints * cnt / W>(st + kQuadPoints * S, ddst, lane);
+    copy_out_full<T, kQuadPoints * cnt / W, kQuadThreads>(st, ydst, lane);
+    if constexpr (STORE)
+      copy_out_full<T, 3 * kQuadPoints * cnt / W, kQuadThreads>(st + kQuadPoints * S, ddst, lane);
   } else {
-    copy_out(st, S, ydst, K, cnt, np, lane, aligned16(ydst));
-    if constexpr (STORE) copy_out(st + kQuadPoints * S, S, ddst, K, cnt, 3 * np, lane, aligned16(ddst));
+    copy_out<kQuadThreads>(st, S, ydst, K, cnt, np, lane, aligned16(ydst));
+    if constexpr (STORE)
+      copy_out<kQuadThreads>(st + kQuadPoints * S, S, ddst, K, cnt, 3 * np, lane, aligned16(ddst));
   }
   __syncthreads();
 }
@@ -243,8 +309,8 @@ constexpr bool quad_has_fast() {
 
 // LT >= 0: l_max = LT known at compile time (MM = LT, degree loops unrolled);
 // LT < 0: l_max = P.L <= MM at run time.  FUSED: the backward is fused
-// (P.gY, P.gxyz); STORE: dY is written.  Dynamic LDS: 64 rows of stride(L)
-// elements, plus 16 rows for the upstream-gradient tile when FUSED.
+// (P.gY, P.gxyz); STORE: dY is written.  Dynamic LDS: 128 rows of stride(L)
+// elements, plus 32 rows for the upstream-gradient tile when FUSED.
 //
 // Full tiles of a one-group plan run a single straight path per tile: the
 // next tile's coordinates are loaded first and the tile's stores follow, so
@@ -254,20 +320,20 @@ constexpr bool quad_has_fast() {
 // of every store of the tile, so the ragged last tile and unaligned outputs
 // take a separate general path.
 template <typename T, int MM, int LT, bool NORM, bool FUSED, bool STORE>
-__global__ __launch_bounds__(kWave) void k_fwd4(FwdParams P) {
+__global__ __launch_bounds__(kQuadThreads) void k_fwd4(FwdParams P) {
   constexpr int B = kQuadBudget<T>;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x;  // 0 .. kQuadThreads - 1
   const int L = LT >= 0 ? LT : P.L;
   const int K = (L + 1) * (L + 1);
   const int smax = plan_stride(L, B);
   T* st = reinterpret_cast<T*>(smem);
-  T* sg = st + kWave * smax;
+  T* sg = st + kQuadThreads * smax;
   const int p = lane >> 2;
   const int r = lane & 3;
   const int lrow = (r == 0) ? p : kQuadPoints + 3 * p + (r - 1);
 
-  if (P.status != nullptr && blockIdx.x == 0) check_offsets(P, lane);
+  if (P.status != nullptr && blockIdx.x == 0 && lane < kWave) check_offsets(P, lane);
 
   const T* xyz = static_cast<const T*>(P.xyz);
   auto tile_body = [&](int64_t tile, T x, T y, T z, auto fast_c) {

@@ -91,28 +91,28 @@ const Tables& tables() {
 
 #if SPH_FAMILY == 1
 KernelInfo SPH_CAT(SPH_CAT(SPH_CAT(fwd_values_, SPH_SUFFIX), _n), SPH_NORM)(int L) {
-  if (!in_range(L)) return KernelInfo{nullptr, 0, 0, 0};
+  if (!in_range(L)) return KernelInfo{nullptr, 0, 0, 0, 0};
   const void* fn = L <= kSpecMax ? tables().spec[L] : tables().buckets[bucket_index(L)];
   const size_t lds = sizeof(T) * kWave * static_cast<size_t>(plan_stride(L, kValueBudget<T>));
-  return KernelInfo{fn, lds, lds, kWave};
+  return KernelInfo{fn, lds, lds, kWave, kWave};
 }
 #elif SPH_FAMILY == 3
 KernelInfo SPH_CAT(SPH_CAT(SPH_CAT(SPH_CAT(SPH_CAT(fwd_derivs_, SPH_SUFFIX), _n), SPH_NORM), _m), SPH_MODE)(int L) {
-  if (!in_range(L)) return KernelInfo{nullptr, 0, 0, 0};
+  if (!in_range(L)) return KernelInfo{nullptr, 0, 0, 0, 0};
   const void* fn = L <= kSpecMax ? tables().spec[L] : tables().buckets[bucket_index(L)];
   const size_t row = sizeof(T) * static_cast<size_t>(plan_stride(L, kQuadBudget<T>));
-  return KernelInfo{fn, row * kWave, row * (kWave + kQuadPoints), kQuadPoints};
+  return KernelInfo{fn, row * kQuadThreads, row * (kQuadThreads + kQuadPoints), kQuadPoints, kQuadThreads};
 }
 #else
 KernelInfo SPH_CAT(bwd_info_, SPH_SUFFIX)(int L) {
-  if (!in_range(L)) return KernelInfo{nullptr, 0, 0, 0};
-  return KernelInfo{tables().bwd, 0, 0, kBwdPointsPerBlock};
+  if (!in_range(L)) return KernelInfo{nullptr, 0, 0, 0, 0};
+  return KernelInfo{tables().bwd, 0, 0, kBwdPointsPerBlock, kBwdThreads};
 }
 
 KernelInfo SPH_CAT(dbwd_info_, SPH_SUFFIX)(int L, int normalize) {
-  if (!in_range(L) || (normalize != 0 && normalize != 1)) return KernelInfo{nullptr, 0, 0, 0};
+  if (!in_range(L) || (normalize != 0 && normalize != 1)) return KernelInfo{nullptr, 0, 0, 0, 0};
   const size_t lds = sizeof(T) * kWave * static_cast<size_t>(plan_stride(L, kDbwdBudget<T>));
-  return KernelInfo{tables().dbwd[normalize][bucket_index(L)], lds, lds, kWave};
+  return KernelInfo{tables().dbwd[normalize][bucket_index(L)], lds, lds, kWave, kWave};
 }
 #endif
 

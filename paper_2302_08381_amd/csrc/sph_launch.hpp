@@ -47,18 +47,19 @@ struct DbwdParams {
 // A kernel's host stub, its dynamic LDS bytes (for the l_max it was looked
 // up with), and for the forward with derivatives the LDS bytes when the
 // backward is fused (the extra upstream-gradient tile); tile_points is the
-// number of points one block covers per tile.
+// number of points one block covers per tile and block its threads.
 struct KernelInfo {
   const void* fn;
   size_t lds_bytes;
   size_t lds_bytes_bwd;
   int tile_points;
+  int block;
 };
 
 // Per element type (suffix f32 / f64) and normalisation; fn == nullptr when
 // the arguments are out of range.
-//   values:      Y only (one lane per point, 64-point tiles)
-//   derivatives: four lanes per point, 16-point tiles; mode
+//   values:      Y only (one lane per point, 64-point tiles, 64 threads)
+//   derivatives: four lanes per point, 32-point tiles, 128 threads; mode
 //                kDerivStore (Y and dY), kDerivFusedStore (Y, dY and the
 //                fused backward), kDerivFused (Y and the fused backward)
 enum DerivMode { kDerivStore = 0, kDerivFusedStore = 1, kDerivFused = 2, kNumDerivModes = 3 };
@@ -83,8 +84,7 @@ KernelInfo bwd_info_f64(int L);
 KernelInfo dbwd_info_f32(int L, int normalize);
 KernelInfo dbwd_info_f64(int L, int normalize);
 
-constexpr int kBwdPointsPerBlock = 16;
-constexpr int kPointsPerBlock = 64;
-constexpr int kBlock = 64;
+constexpr int kBwdPointsPerBlock = 32;
+constexpr int kBwdThreads = 128;
 
 }  // namespace sph
