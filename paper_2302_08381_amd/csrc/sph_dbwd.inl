@@ -26,10 +26,13 @@
 
 namespace sph {
 
+// Per-point LDS budget: one group of degrees up to l_max = 12 (float) or 8
+// (double), a 64-row tile of about 44 KB whose rows are contiguous in global
+// memory.
 template <typename T>
-inline constexpr int kDbwdBudget = 84;
+inline constexpr int kDbwdBudget = 172;
 template <>
-inline constexpr int kDbwdBudget<double> = 66;
+inline constexpr int kDbwdBudget<double> = 86;
 
 template <typename T>
 struct DbwdAcc {

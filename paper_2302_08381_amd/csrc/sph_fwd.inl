@@ -10,11 +10,13 @@
 
 namespace sph {
 
-// Per-point LDS budget (elements of one group of degrees).
+// Per-point LDS budget (elements of one group of degrees): one group up to
+// l_max = 12 (float) or 8 (double), a 64-row tile of about 44 KB whose rows
+// are contiguous in global memory.
 template <typename T>
-inline constexpr int kValueBudget = 84;
+inline constexpr int kValueBudget = 172;
 template <>
-inline constexpr int kValueBudget<double> = 66;
+inline constexpr int kValueBudget<double> = 86;
 
 // CSR consistency check, done by block 0 only (single writer, no atomics).
 __device__ __forceinline__ void check_offsets(const FwdParams& P, int lane) {

@@ -1,10 +1,10 @@
 // Forward with derivatives, four lanes per point.
 //
-// A block of two waves takes a tile of 32 points; thread 4p + r evaluates
-// point p of the tile and emits component r of it: r = 0 the values, r = 1, 2,
-// 3 the d/dx, d/dy, d/dz derivatives.  Every lane runs the same instructions
-// (the four components differ only in per-lane weights, so nothing
-// diverges):
+// A block of one or two waves takes a tile of 16 or 32 points; thread 4p + r
+// evaluates point p of the tile and emits component r of it: r = 0 the
+// values, r = 1, 2, 3 the d/dx, d/dy, d/dz derivatives.  Every lane runs the
+// same instructions (the four components differ only in per-lane weights, so
+// nothing diverges):
 //
 //   value(+m) = A c_m + B P+ ,  value(-m) = A s_m + B P-
 //   A = w_q Qt_l^m + w_t Tm + w_c Cm        (Tm = gxy Qt_{l-1}^{m+1}, Cm = gz Qt_{l-1}^m)
@@ -17,14 +17,12 @@
 // rule (d_a Yt(u) - l u_a Yt(u)) / r folds into A -> (A - l u_a Qt) / r and
 // B -> B / r.
 //
-// The LDS tile is laid out exactly as the global arrays: 32 value rows
-// (the points' Y rows) followed by 96 derivative rows (dY[p][a]); with one
+// The LDS tile is laid out exactly as the global arrays: the P value rows
+// (the points' Y rows) followed by 3P derivative rows (dY[p][a]); with one
 // group of degrees both blocks are contiguous in global memory and are
-// copied out with 16-byte stores.  A tile of 32 points makes each block's
-// share of Y and dY a whole number of 128-byte lines for every odd K (32 K
-// and 96 K floats), so no cache line is written by two blocks; with 16-point
-// tiles every other block boundary splits a line, and such partial lines
-// cost write bandwidth.  The fused backward (batched entry) adds
+// copied out with 16-byte stores.  Tiles whose share of Y and dY is a whole
+// number of 128-byte lines write no cache line from two blocks; a line split
+// between blocks costs write bandwidth.  The fused backward (batched entry) adds
 // sum_k gY[p,k] dY[p,a,k] in thread 4p + a + 1, which then owns
 // grad_xyz[p,a].
 #pragma once
@@ -35,15 +33,27 @@
 
 namespace sph {
 
-constexpr int kQuadWaves = 2;                       // waves per block
-constexpr int kQuadPoints = 16 * kQuadWaves;        // points per tile (one block)
-constexpr int kQuadThreads = kWave * kQuadWaves;    // threads per block, 4 per point
+// Waves per block.  Float kernels for a compile-time l_max <= 8 (K <= 81)
+// take a 32-point tile on two waves, which makes each block's share of Y and
+// dY a whole number of 128-byte lines (32 K and 96 K floats, K odd).  Every
+// other kernel takes a 16-point tile on one wave so that the one-group LDS
+// tile of a larger K still fits; for double a 16-point share is already a
+// whole number of lines.  LT < 0: run-time l_max.
+template <typename T>
+constexpr int quad_waves(int LT) {
+  return (std::is_same_v<T, float> && LT >= 0 && LT <= 8) ? 2 : 1;
+}
+constexpr int kQuadWavePoints = 16;  // points per wave (four lanes per point)
 
 // Per-point LDS budget (elements of one component of one group of degrees).
+// A one-wave tile (64 rows) then stays near 44 KB, and l_max <= 12 (float)
+// or l_max <= 8 (double) is evaluated as one group of degrees, whose rows are
+// contiguous in global memory.  Larger l_max split into groups of degrees
+// whose partial rows are written with 4-byte stores.
 template <typename T>
-inline constexpr int kQuadBudget = 84;
+inline constexpr int kQuadBudget = 172;
 template <>
-inline constexpr int kQuadBudget<double> = 42;
+inline constexpr int kQuadBudget<double> = 86;
 
 template <typename T>
 struct Role {
@@ -201,10 +211,12 @@ __device__ __forceinline__ void emit4_ct(const Role<T>& ro, const Point<T>& pt, 
   }
 }
 
-template <typename T, int MM, bool NORM, bool UNROLL, bool FUSED, bool STORE>
+template <typename T, int NW, int MM, bool NORM, bool UNROLL, bool FUSED, bool STORE>
 __device__ __forceinline__ void fwd4_group(const Role<T>& ro, const Point<T>& pt, int la, int lb, int K,
                                            int64_t p0, int np, int lane, int lrow, const FwdParams& P,
                                            T* st, T* sg, T& acc) {
+  constexpr int PT = kQuadWavePoints * NW;
+  constexpr int NT = kWave * NW;
   const int kb = la * la;
   const int cnt = lb * lb - kb;
   const int S = cnt | 1;
@@ -212,7 +224,7 @@ __device__ __forceinline__ void fwd4_group(const Role<T>& ro, const Point<T>& pt
   const int p = lane >> 2;
   if (bwd) {
     const T* src = static_cast<const T*>(P.gY) + p0 * K + kb;
-    copy_in<kQuadThreads>(sg, S, src, K, cnt, np, lane, aligned16(src));
+    copy_in<NT>(sg, S, src, K, cnt, np, lane, aligned16(src));
   }
   emit4<T, MM, NORM, UNROLL>(ro, pt, la, lb, st + lrow * S - kb);
   __syncthreads();
@@ -231,28 +243,30 @@ __device__ __forceinline__ void fwd4_group(const Role<T>& ro, const Point<T>& pt
   }
   {
     T* dst = static_cast<T*>(P.Y) + p0 * K + kb;
-    copy_out<kQuadThreads>(st, S, dst, K, cnt, np, lane, aligned16(dst));
+    copy_out<NT>(st, S, dst, K, cnt, np, lane, aligned16(dst));
   }
   if constexpr (STORE) {
     T* dst = static_cast<T*>(P.dY) + p0 * 3 * K + kb;
-    copy_out<kQuadThreads>(st + kQuadPoints * S, S, dst, K, cnt, 3 * np, lane, aligned16(dst));
+    copy_out<NT>(st + PT * S, S, dst, K, cnt, 3 * np, lane, aligned16(dst));
   }
   __syncthreads();
 }
 
-// One compile-time group of degrees [LA, LB).  FAST: a full 16-point tile of
+// One compile-time group of degrees [LA, LB).  FAST: a full tile of
 // a one-group plan with 16-byte aligned outputs, copied out with the
 // fixed-size unpredicated copy; otherwise the general copy.
-template <typename T, int MM, bool NORM, bool FUSED, bool STORE, bool FAST, int LA, int LB>
+template <typename T, int NW, int MM, bool NORM, bool FUSED, bool STORE, bool FAST, int LA, int LB>
 __device__ __forceinline__ void fwd4_group_ct(const Role<T>& ro, const Point<T>& pt, int K, int64_t p0, int np,
                                               int lane, int lrow, const FwdParams& P, T* st, T* sg, T& acc) {
+  constexpr int PT = kQuadWavePoints * NW;
+  constexpr int NT = kWave * NW;
   constexpr int kb = LA * LA;
   constexpr int cnt = LB * LB - kb;
   constexpr int S = cnt | 1;
   const int p = lane >> 2;
   if constexpr (FUSED) {
     const T* src = static_cast<const T*>(P.gY) + p0 * K + kb;
-    copy_in<kQuadThreads>(sg, S, src, K, cnt, np, lane, aligned16(src));
+    copy_in<NT>(sg, S, src, K, cnt, np, lane, aligned16(src));
   }
   emit4_ct<T, MM, NORM, LA, LB>(ro, pt, st + lrow * S - kb);
   __syncthreads();
@@ -273,24 +287,24 @@ __device__ __forceinline__ void fwd4_group_ct(const Role<T>& ro, const Point<T>&
   if constexpr (FAST) {
     static_assert(S == cnt && kb == 0, "fast path needs one contiguous group");
     constexpr int W = Vec16<T>::n;
-    copy_out_full<T, kQuadPoints * cnt / W, kQuadThreads>(st, ydst, lane);
+    copy_out_full<T, PT * cnt / W, NT>(st, ydst, lane);
     if constexpr (STORE)
-      copy_out_full<T, 3 * kQuadPoints * cnt / W, kQuadThreads>(st + kQuadPoints * S, ddst, lane);
+      copy_out_full<T, 3 * PT * cnt / W, NT>(st + PT * S, ddst, lane);
   } else {
-    copy_out<kQuadThreads>(st, S, ydst, K, cnt, np, lane, aligned16(ydst));
+    copy_out<NT>(st, S, ydst, K, cnt, np, lane, aligned16(ydst));
     if constexpr (STORE)
-      copy_out<kQuadThreads>(st + kQuadPoints * S, S, ddst, K, cnt, 3 * np, lane, aligned16(ddst));
+      copy_out<NT>(st + PT * S, S, ddst, K, cnt, 3 * np, lane, aligned16(ddst));
   }
   __syncthreads();
 }
 
-template <typename T, int MM, bool NORM, bool FUSED, bool STORE, bool FAST, int LT, int... Gs>
+template <typename T, int NW, int MM, bool NORM, bool FUSED, bool STORE, bool FAST, int LT, int... Gs>
 __device__ __forceinline__ void fwd4_groups_ct(std::integer_sequence<int, Gs...>, const Role<T>& ro,
                                                const Point<T>& pt, int K, int64_t p0, int np, int lane,
                                                int lrow, const FwdParams& P, T* st, T* sg, T& acc) {
   constexpr Plan PL = make_plan(LT, kQuadBudget<T>);
-  (fwd4_group_ct<T, MM, NORM, FUSED, STORE, FAST, PL.lo[Gs], PL.hi[Gs]>(ro, pt, K, p0, np, lane, lrow, P, st, sg,
-                                                                        acc),
+  (fwd4_group_ct<T, NW, MM, NORM, FUSED, STORE, FAST, PL.lo[Gs], PL.hi[Gs]>(ro, pt, K, p0, np, lane, lrow, P, st,
+                                                                            sg, acc),
    ...);
 }
 
@@ -309,8 +323,8 @@ constexpr bool quad_has_fast() {
 
 // LT >= 0: l_max = LT known at compile time (MM = LT, degree loops unrolled);
 // LT < 0: l_max = P.L <= MM at run time.  FUSED: the backward is fused
-// (P.gY, P.gxyz); STORE: dY is written.  Dynamic LDS: 128 rows of stride(L)
-// elements, plus 32 rows for the upstream-gradient tile when FUSED.
+// (P.gY, P.gxyz); STORE: dY is written.  Dynamic LDS: 4 PT rows of
+// stride(L) elements, plus PT rows for the upstream-gradient tile when FUSED.
 //
 // Full tiles of a one-group plan run a single straight path per tile: the
 // next tile's coordinates are loaded first and the tile's stores follow, so
@@ -320,37 +334,40 @@ constexpr bool quad_has_fast() {
 // of every store of the tile, so the ragged last tile and unaligned outputs
 // take a separate general path.
 template <typename T, int MM, int LT, bool NORM, bool FUSED, bool STORE>
-__global__ __launch_bounds__(kQuadThreads) void k_fwd4(FwdParams P) {
+__global__ __launch_bounds__(kWave * quad_waves<T>(LT)) void k_fwd4(FwdParams P) {
+  constexpr int NW = quad_waves<T>(LT);
+  constexpr int PT = kQuadWavePoints * NW;  // points per tile
+  constexpr int NT = kWave * NW;            // threads per block
   constexpr int B = kQuadBudget<T>;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int lane = threadIdx.x;  // 0 .. kQuadThreads - 1
+  const int lane = threadIdx.x;  // 0 .. NT - 1
   const int L = LT >= 0 ? LT : P.L;
   const int K = (L + 1) * (L + 1);
   const int smax = plan_stride(L, B);
   T* st = reinterpret_cast<T*>(smem);
-  T* sg = st + kQuadThreads * smax;
+  T* sg = st + NT * smax;
   const int p = lane >> 2;
   const int r = lane & 3;
-  const int lrow = (r == 0) ? p : kQuadPoints + 3 * p + (r - 1);
+  const int lrow = (r == 0) ? p : PT + 3 * p + (r - 1);
 
   if (P.status != nullptr && blockIdx.x == 0 && lane < kWave) check_offsets(P, lane);
 
   const T* xyz = static_cast<const T*>(P.xyz);
   auto tile_body = [&](int64_t tile, T x, T y, T z, auto fast_c) {
     constexpr bool FAST = decltype(fast_c)::value;
-    const int64_t p0 = tile * kQuadPoints;
-    const int np = FAST ? kQuadPoints : static_cast<int>(P.n - p0 < kQuadPoints ? P.n - p0 : kQuadPoints);
+    const int64_t p0 = tile * PT;
+    const int np = FAST ? PT : static_cast<int>(P.n - p0 < PT ? P.n - p0 : PT);
     const Point<T> pt = make_point<T, NORM>(x, y, z);
     const Role<T> ro = make_role<T, NORM>(r, pt);
     T acc = T(0);
     if constexpr (LT >= 0) {
       constexpr Plan PL = make_plan(LT, B);
-      fwd4_groups_ct<T, MM, NORM, FUSED, STORE, FAST, LT>(std::make_integer_sequence<int, PL.ng>{}, ro, pt, K,
+      fwd4_groups_ct<T, NW, MM, NORM, FUSED, STORE, FAST, LT>(std::make_integer_sequence<int, PL.ng>{}, ro, pt, K,
                                                           p0, np, lane, lrow, P, st, sg, acc);
     } else {
       for (int la = 0; la <= L;) {
         const int lb = group_end(la, L, B);
-        fwd4_group<T, MM, NORM, false, FUSED, STORE>(ro, pt, la, lb, K, p0, np, lane, lrow, P, st, sg, acc);
+        fwd4_group<T, NW, MM, NORM, false, FUSED, STORE>(ro, pt, la, lb, K, p0, np, lane, lrow, P, st, sg, acc);
         la = lb;
       }
     }
@@ -368,27 +385,27 @@ __global__ __launch_bounds__(kQuadThreads) void k_fwd4(FwdParams P) {
   constexpr bool kFast = quad_has_fast<T, LT>();
   const bool aligned = aligned16(P.Y) && (!STORE || aligned16(P.dY));
   if (kFast && aligned) {
-    const int64_t nfull = P.n / kQuadPoints;
+    const int64_t nfull = P.n / PT;
     if (static_cast<int64_t>(blockIdx.x) < nfull) {
       T nx, ny, nz;
-      load_point(blockIdx.x * kQuadPoints + p, nx, ny, nz);
+      load_point(blockIdx.x * PT + p, nx, ny, nz);
       for (int64_t tile = blockIdx.x; tile < nfull; tile += gridDim.x) {
         const T x = nx, y = ny, z = nz;
         // next full tile (clamped, so the load is unconditional)
         const int64_t nt = tile + gridDim.x < nfull ? tile + gridDim.x : tile;
-        load_point(nt * kQuadPoints + p, nx, ny, nz);
+        load_point(nt * PT + p, nx, ny, nz);
         tile_body(tile, x, y, z, std::integral_constant<bool, kFast>{});
       }
     }
-    if (P.n % kQuadPoints != 0 && nfull % gridDim.x == blockIdx.x) {
+    if (P.n % PT != 0 && nfull % gridDim.x == blockIdx.x) {
       T x = T(0), y = T(0), z = T(0);
-      if (nfull * kQuadPoints + p < P.n) load_point(nfull * kQuadPoints + p, x, y, z);
+      if (nfull * PT + p < P.n) load_point(nfull * PT + p, x, y, z);
       tile_body(nfull, x, y, z, std::false_type{});
     }
   } else {
-    for (int64_t tile = blockIdx.x; tile * kQuadPoints < P.n; tile += gridDim.x) {
+    for (int64_t tile = blockIdx.x; tile * PT < P.n; tile += gridDim.x) {
       T x = T(0), y = T(0), z = T(0);
-      if (tile * kQuadPoints + p < P.n) load_point(tile * kQuadPoints + p, x, y, z);
+      if (tile * PT + p < P.n) load_point(tile * PT + p, x, y, z);
       tile_body(tile, x, y, z, std::false_type{});
     }
   }

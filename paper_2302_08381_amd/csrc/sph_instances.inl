@@ -22,10 +22,11 @@ bool in_range(int L) { return L >= 0 && L <= kMaxL; }
 
 #if SPH_FAMILY == 1 || SPH_FAMILY == 3
 constexpr bool kNorm = SPH_NORM != 0;
-// float32 specialises l_max <= 8 at compile time (degree loops unrolled,
-// coefficients as literals); everything else uses the run-time-degree
-// kernel of the smallest m-extent bucket that covers l_max.
-constexpr int kSpecMax = std::is_same_v<T, float> ? 8 : -1;
+// l_max <= 12 (float) and l_max <= 8 (double) are specialised at compile
+// time (degree loops unrolled, coefficients as literals, order-m terms
+// tabulated); larger l_max use the run-time-degree kernel of the smallest
+// m-extent bucket that covers l_max.
+constexpr int kSpecMax = std::is_same_v<T, float> ? 12 : 8;
 constexpr int kSpecSlots = kSpecMax + 1 > 0 ? kSpecMax + 1 : 1;
 
 #if SPH_FAMILY == 1
@@ -101,7 +102,9 @@ KernelInfo SPH_CAT(SPH_CAT(SPH_CAT(SPH_CAT(SPH_CAT(fwd_derivs_, SPH_SUFFIX), _n)
   if (!in_range(L)) return KernelInfo{nullptr, 0, 0, 0, 0};
   const void* fn = L <= kSpecMax ? tables().spec[L] : tables().buckets[bucket_index(L)];
   const size_t row = sizeof(T) * static_cast<size_t>(plan_stride(L, kQuadBudget<T>));
-  return KernelInfo{fn, row * kQuadThreads, row * (kQuadThreads + kQuadPoints), kQuadPoints, kQuadThreads};
+  const int nw = quad_waves<T>(L <= kSpecMax ? L : -1);  // as the kernel's own tile
+  const int pts = kQuadWavePoints * nw, thr = kWave * nw;
+  return KernelInfo{fn, row * static_cast<size_t>(4 * pts), row * static_cast<size_t>(5 * pts), pts, thr};
 }
 #else
 KernelInfo SPH_CAT(bwd_info_, SPH_SUFFIX)(int L) {
