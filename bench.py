@@ -13,6 +13,11 @@ figures, the accuracy of sampled rows against the float64 oracle, and the
 oracle itself timed on the host cores (a bounded sample).
 
     python bench.py [--gpus 1] [--steps 50] [--warmup 10] [--no-cpu-baseline]
+
+Profiling (rocprofv3 runs of `bench.py --profile`, commands in
+PROFILE_COMMANDS) and their summaries under profiles/:
+
+    python bench.py --summarize DIR    # DIR holds the rocprofv3 output folders
 """
 from __future__ import annotations
 
@@ -57,6 +62,101 @@ def load_traffic(kind: str):
         return None
     k = t.get("kernels", {}).get(kind)
     return None if k is None else float(k["hbm_bytes_per_launch"])
+
+
+# The rocprofv3 runs whose output --summarize reads ({out}: output folder,
+# {repo}: this repository).  Run from /tmp with TMPDIR=/tmp.  Counters are
+# collected in runs of their own, one counter per run.
+PROFILE_COMMANDS = {
+    "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d {out}/prof_trace -o run -- "
+             "python3 {repo}/bench.py --profile --steps 20 --warmup 3",
+    "fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d {out}/pmc_fetch -o run -- "
+             "python3 {repo}/bench.py --profile --steps 3 --warmup 1",
+    "write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d {out}/pmc_write -o run -- "
+             "python3 {repo}/bench.py --profile --steps 3 --warmup 1",
+}
+KERNEL_ROLES = {"forward": "k_fwd4<", "backward": "k_bwd<"}
+REFERENCE_COPY = "copyBuffer"  # torch's device-to-device copy of the profile run
+REFERENCE_COPY_BYTES = 1 << 30
+
+
+def _counter_per_dispatch(path: str) -> dict:
+    """{kernel name: [counter value per dispatch]} from a rocprofv3 counter CSV."""
+    import csv
+    per = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            key = (r["Dispatch_Id"], r["Kernel_Name"])
+            per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+    out = {}
+    for (_, name), v in per.items():
+        out.setdefault(name, []).append(v)
+    return out
+
+
+def summarize(outdir: str) -> None:
+    """Write profiles/kernels_l8_f32.md (kernel trace statistics) and
+    profiles/traffic_l8_f32.{json,md} (HBM bytes per launch from FETCH_SIZE and
+    WRITE_SIZE, each scaled by what the counter reads for the profile run's
+    1 GiB reference copy)."""
+    import csv
+    prof = os.path.join(ROOT, "profiles")
+    os.makedirs(prof, exist_ok=True)
+    K = (L_MAX + 1) ** 2
+    alg = N_POINTS * 4 * (3 + 4 * K)
+    cmds = {k: v.format(out="/root/repo/gpurun_out", repo="/root/repo") for k, v in PROFILE_COMMANDS.items()}
+
+    with open(os.path.join(outdir, "prof_trace", "run_kernel_stats.csv")) as f:
+        stats = list(csv.DictReader(f))
+    lines = ["# Kernel trace: forward (Y+dY) and backward, l_max = 8, float32, N = 1,000,000", "",
+             "Command (from /tmp, TMPDIR=/tmp):", "", "    " + cmds["trace"], "",
+             f"Kernel sources hash: {kernel_hash()}", "",
+             "| kernel | calls | mean us | min us | max us | share % | algorithmic GB/s at mean |",
+             "|---|---|---|---|---|---|---|"]
+    for r in stats:
+        name = r["Name"]
+        mean = float(r["AverageNs"]) * 1e-9
+        gbs = ""
+        if any(tag in name for tag in KERNEL_ROLES.values()):
+            gbs = f"{alg / mean / 1e9:.0f}"
+        lines.append(f"| `{name}` | {r['Calls']} | {mean * 1e6:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                     f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} | {gbs} |")
+    lines += ["", f"Algorithmic bytes per launch of either kernel: N * 4 * (3 + 4K) = {alg} (K = {K})."]
+    with open(os.path.join(prof, "kernels_l8_f32.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+    fetch = _counter_per_dispatch(os.path.join(outdir, "pmc_fetch", "run_counter_collection.csv"))
+    write = _counter_per_dispatch(os.path.join(outdir, "pmc_write", "run_counter_collection.csv"))
+
+    def mean_of(tbl, tag):
+        vals = [v for name, vs in tbl.items() if tag in name for v in vs]
+        return sum(vals) / len(vals) if vals else None
+
+    fscale = REFERENCE_COPY_BYTES / (mean_of(fetch, REFERENCE_COPY) * 1024)
+    wscale = REFERENCE_COPY_BYTES / (mean_of(write, REFERENCE_COPY) * 1024)
+    t = {"kernel_hash": kernel_hash(), "commands": {"fetch": cmds["fetch"], "write": cmds["write"]},
+         "reference_copy_bytes": REFERENCE_COPY_BYTES,
+         "scale": {"FETCH_SIZE": fscale, "WRITE_SIZE": wscale}, "kernels": {}}
+    md = ["# HBM traffic per launch: forward (Y+dY) and backward, l_max = 8, float32, N = 1,000,000", "",
+          "Commands (from /tmp, TMPDIR=/tmp):", "", "    " + cmds["fetch"], "    " + cmds["write"], "",
+          f"Kernel sources hash: {kernel_hash()}", "",
+          f"Scale factors: bytes = counter KiB * 1024 * factor, with the factor set so that the "
+          f"1 GiB reference copy reads and writes 1 GiB: FETCH_SIZE x{fscale:.3f}, WRITE_SIZE x{wscale:.3f}.", "",
+          "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes (scaled) | algorithmic bytes | ratio |",
+          "|---|---|---|---|---|---|"]
+    for role, tag in KERNEL_ROLES.items():
+        fk, wk = mean_of(fetch, tag), mean_of(write, tag)
+        if fk is None or wk is None:
+            continue
+        hbm = (fk * fscale + wk * wscale) * 1024
+        t["kernels"][role] = {"fetch_kib": fk, "write_kib": wk, "hbm_bytes_per_launch": hbm,
+                              "algorithmic_bytes": alg}
+        md.append(f"| {role} | {fk:.0f} | {wk:.0f} | {hbm:.4g} | {alg:.4g} | {hbm / alg:.3f} |")
+    with open(os.path.join(prof, "traffic_l8_f32.json"), "w") as f:
+        json.dump(t, f, indent=1)
+    with open(os.path.join(prof, "traffic_l8_f32.md"), "w") as f:
+        f.write("\n".join(md) + "\n")
+    print("\n".join(lines + [""] + md))
 
 
 def cpu_baseline(n_sample: int = 200_000, chunk: int = 20_000):
@@ -190,7 +290,12 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary measurements")
     ap.add_argument("--profile", action="store_true",
                     help="only run warmup + steps (and a 1 GiB reference copy), for rocprofv3")
+    ap.add_argument("--summarize", metavar="DIR",
+                    help="write the profiles/ summaries from the rocprofv3 output in DIR (no GPU)")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(args.summarize)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path has no "
               "cross-GPU step and this build runs on a single MI355X.", file=sys.stderr)
@@ -226,7 +331,7 @@ def main():
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"profile_run": True, "steps": args.steps, "reference_copy_bytes": 2 * a.numel() * 4}))
+        print(json.dumps({"profile_run": True, "steps": args.steps, "reference_copy_bytes_each_way": a.numel() * 4}))
         return
 
     stream = torch.cuda.current_stream(dev)  # the launch stream of both kernels

@@ -1,15 +1,17 @@
 // Backward (vector-Jacobian product) with stored derivatives:
 //   gxyz[i,a] = sum_k gY[i,k] dY[i,a,k]
 // A streaming contraction (no MFMA: one short dot product per point and
-// axis).  A block of 128 threads takes 32 points (for odd K the block's share
-// of gY and dY is then a whole number of 128-byte lines).  The gY rows and the
-// 96 dY rows of those points are copied into LDS with coalesced (16-byte when
-// possible) loads in chunks of at most KC columns, kBwdBatch loads in flight
-// per thread: deep enough that one round trip covers a chunk, since at the
-// occupancy the LDS tile allows the kernel is bound by read latency.  Thread
-// (p, q) then sums columns k = q (mod 4) of point p for the three axes, and
-// the four partial sums are combined with two lane exchanges.  The summation
-// order is fixed, so the result is deterministic.
+// axis).  A block of NW waves takes 16 NW points: two waves (32 points) for
+// float with K <= 86, whose share of gY and dY is then a whole number of
+// 128-byte lines for odd K, and one wave (16 points) otherwise.  The gY rows
+// and the 3 x 16 NW dY rows of those points are copied into LDS with coalesced
+// (16-byte when possible) loads in balanced chunks of at most KC columns (the
+// tile stays near 44 KB), kBwdBatch loads in flight per thread: deep enough
+// that one round trip covers a chunk, since at the occupancy the LDS tile
+// allows the kernel is bound by read latency.  Thread (p, q) then sums
+// columns k = q (mod 4) of point p for the three axes, and the four partial
+// sums are combined with two lane exchanges.  The summation order is fixed,
+// so the result is deterministic.
 #pragma once
 
 #include "sph_device.hpp"
@@ -17,16 +19,23 @@
 
 namespace sph {
 
+// Columns per chunk for blocks of NW waves.
+template <typename T, int NW>
+constexpr int bwd_chunk() {
+  return (std::is_same_v<T, float> ? 172 : 86) / NW;
+}
+// Waves per block for K components.
 template <typename T>
-inline constexpr int kBwdChunk = 84;
-template <>
-inline constexpr int kBwdChunk<double> = 42;
+constexpr int bwd_waves(int K) {
+  return (std::is_same_v<T, float> && K <= bwd_chunk<T, 2>()) ? 2 : 1;
+}
 constexpr int kBwdBatch = 16;
 
-template <typename T>
-__global__ __launch_bounds__(kBwdThreads) void k_bwd(BwdParams P) {
-  constexpr int PP = kBwdPointsPerBlock;  // 32 points per block
-  constexpr int KC = kBwdChunk<T>;
+template <typename T, int NW>
+__global__ __launch_bounds__(kWave * NW) void k_bwd(BwdParams P) {
+  constexpr int PP = 16 * NW;   // points per block
+  constexpr int NT = kWave * NW;
+  constexpr int KC = bwd_chunk<T, NW>();
   constexpr int SC = KC | 1;
   __shared__ __align__(16) T sg[PP * SC];
   __shared__ __align__(16) T sd[3 * PP * SC];
@@ -39,13 +48,15 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(BwdParams P) {
   const int np = static_cast<int>(P.n - p0 < PP ? P.n - p0 : PP);
   const T* gY = static_cast<const T*>(P.gY) + p0 * K;
   const T* dY = static_cast<const T*>(P.dY) + p0 * 3 * K;
+  const int nch = (K + KC - 1) / KC;
+  const int ch = (K + nch - 1) / nch;  // balanced chunk width, <= KC
 
   T a0 = T(0), a1 = T(0), a2 = T(0);
-  for (int kc0 = 0; kc0 < K; kc0 += KC) {
-    const int cnt = (K - kc0) < KC ? (K - kc0) : KC;
+  for (int kc0 = 0; kc0 < K; kc0 += ch) {
+    const int cnt = (K - kc0) < ch ? (K - kc0) : ch;
     const int S = cnt | 1;
-    copy_in<kBwdThreads, kBwdBatch>(sg, S, gY + kc0, K, cnt, np, lane, aligned16(gY + kc0));
-    copy_in<kBwdThreads, kBwdBatch>(sd, S, dY + kc0, K, cnt, 3 * np, lane, aligned16(dY + kc0));
+    copy_in<NT, kBwdBatch>(sg, S, gY + kc0, K, cnt, np, lane, aligned16(gY + kc0));
+    copy_in<NT, kBwdBatch>(sd, S, dY + kc0, K, cnt, 3 * np, lane, aligned16(dY + kc0));
     __syncthreads();
     if (pl < np) {
       const T* g = sg + pl * S;

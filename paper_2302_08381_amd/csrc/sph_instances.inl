@@ -74,11 +74,12 @@ void fill_dbwd(const void** out, std::integer_sequence<int, Is...>) {
 
 struct Tables {
   const void* dbwd[2][kNumBuckets];
-  const void* bwd;
+  const void* bwd[2];  // one and two waves per block
   Tables() {
     fill_dbwd<false>(dbwd[0], Buckets{});
     fill_dbwd<true>(dbwd[1], Buckets{});
-    bwd = reinterpret_cast<const void*>(&k_bwd<T>);
+    bwd[0] = reinterpret_cast<const void*>(&k_bwd<T, 1>);
+    bwd[1] = reinterpret_cast<const void*>(&k_bwd<T, 2>);
   }
 };
 #endif
@@ -109,7 +110,8 @@ KernelInfo SPH_CAT(SPH_CAT(SPH_CAT(SPH_CAT(SPH_CAT(fwd_derivs_, SPH_SUFFIX), _n)
 #else
 KernelInfo SPH_CAT(bwd_info_, SPH_SUFFIX)(int L) {
   if (!in_range(L)) return KernelInfo{nullptr, 0, 0, 0, 0};
-  return KernelInfo{tables().bwd, 0, 0, kBwdPointsPerBlock, kBwdThreads};
+  const int nw = bwd_waves<T>((L + 1) * (L + 1));
+  return KernelInfo{tables().bwd[nw - 1], 0, 0, 16 * nw, kWave * nw};
 }
 
 KernelInfo SPH_CAT(dbwd_info_, SPH_SUFFIX)(int L, int normalize) {

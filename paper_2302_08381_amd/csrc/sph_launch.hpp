@@ -84,7 +84,4 @@ KernelInfo bwd_info_f64(int L);
 KernelInfo dbwd_info_f32(int L, int normalize);
 KernelInfo dbwd_info_f64(int L, int normalize);
 
-constexpr int kBwdPointsPerBlock = 32;
-constexpr int kBwdThreads = 128;
-
 }  // namespace sph
