@@ -135,9 +135,12 @@ int32_t sph_double_backward(const void* xyz, const void* grad_Y, const void* v,
  * owns rows offsets[e] .. offsets[e+1]-1 of xyz (Sec. III: the harmonics of
  * the neighbours of each selected atom).  Every output follows the
  * concatenated row order.  The launch is a persistent kernel replayed from a
- * cached hipGraph; on the first call for a (dtype, l_max, normalize, outputs)
- * combination the library times the persistent-grid sizes on the caller's
- * own buffers and keeps the fastest (the timing synchronises the host once).
+ * cached hipGraph.  On the first call for a (dtype, l_max, normalize,
+ * outputs) combination the library times its candidate launches on the
+ * caller's own buffers and keeps the fastest; the timing synchronises the
+ * host once.  The candidates are every kernel variant (the unrolled
+ * compile-time kernel on its default tile, the same on a 16-point tile, the
+ * run-time-degree kernel) crossed with every persistent-grid size.
  *   xyz        in  [n_points,3]
  *   offsets    in  int64 [n_env+1], DEVICE memory
  *   n_env      number of environments (>= 0)
@@ -161,20 +164,37 @@ int32_t sph_batched_compute(const void* xyz, const int64_t* offsets, int64_t n_e
 /*
  * sph_batched_set_options -- batched-path controls (process-wide).
  *   use_graph  1: replay cached hipGraphs (default); 0: plain launches
- *   autotune   1: time the persistent-grid sizes on first use (default);
+ *   autotune   1: time the candidate launches on first use (default);
  *              0: use the built-in defaults
  */
 int32_t sph_batched_set_options(int32_t use_graph, int32_t autotune);
 
 /*
- * sph_batched_get_config -- the launch shape chosen for a combination, as
- * "blocks_per_cu=<b> tile_points=<t>" in buf (NUL-terminated, at most len
- * bytes); blocks_per_cu = 0 means one tile per block.  Returns
- * SPH_ERR_INVALID if nothing was chosen yet.
+ * sph_batched_get_config -- the launch chosen for a combination, as
+ * "kernel=<v> blocks_per_cu=<b> tile_points=<t>" in buf (NUL-terminated, at
+ * most len bytes).  v is default, tile16 or runtime_degree;
+ * blocks_per_cu = 0 means one tile per block.  Returns SPH_ERR_INVALID if
+ * nothing was chosen yet.
  */
 int32_t sph_batched_get_config(int32_t l_max, int32_t normalize, int32_t dtype,
                                int32_t store_dY, int32_t with_backward,
                                char* buf, int32_t len);
+
+/*
+ * sph_batched_set_config -- fixes the launch of a combination instead of
+ * timing the candidates (for callers that need a known launch, e.g. before
+ * capturing a graph, and for testing every variant).
+ *   variant        0 default, 1 tile16, 2 runtime_degree (as in
+ *                  sph_batched_get_config)
+ *   blocks_per_cu  0 .. 64 (0: one tile per block)
+ * Returns SPH_ERR_INVALID for an unknown combination, a variant that does
+ * not exist for it (tile16 exists only for float, l_max <= 8 with dY or the
+ * backward; runtime_degree only where the default is unrolled) or an out of
+ * range blocks_per_cu; SPH_ERR_LMAX for l_max out of range.
+ */
+int32_t sph_batched_set_config(int32_t l_max, int32_t normalize, int32_t dtype,
+                               int32_t store_dY, int32_t with_backward,
+                               int32_t variant, int32_t blocks_per_cu);
 
 #ifdef __cplusplus
 }

@@ -20,6 +20,7 @@ from ._native import (  # noqa: F401
     sph_backward,
     sph_batched_compute,
     sph_batched_get_config,
+    sph_batched_set_config,
     sph_batched_set_options,
     sph_compute,
     sph_compute_with_gradients,

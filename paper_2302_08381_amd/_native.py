@@ -47,6 +47,7 @@ _SIGNATURES = {
     "sph_batched_compute": (_i32, [_vp, _vp, _i64, _i64, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "sph_batched_set_options": (_i32, [_i32, _i32]),
     "sph_batched_get_config": (_i32, [_i32, _i32, _i32, _i32, _i32, ctypes.c_char_p, _i32]),
+    "sph_batched_set_config": (_i32, [_i32, _i32, _i32, _i32, _i32, _i32, _i32]),
 }
 
 
@@ -259,3 +260,16 @@ def sph_batched_get_config(l_max: int, normalize: bool, dtype: torch.dtype, stor
     st = lib().sph_batched_get_config(int(l_max), int(bool(normalize)), code, int(bool(store_dY)),
                                       int(bool(with_backward)), buf, 128)
     return buf.value.decode() if st == SPH_OK else None
+
+
+BATCHED_VARIANTS = {"default": 0, "tile16": 1, "runtime_degree": 2}
+
+
+def sph_batched_set_config(l_max: int, normalize: bool, dtype: torch.dtype, store_dY: bool,
+                           with_backward: bool, variant: str = "default", blocks_per_cu: int = 0):
+    """Fix the batched launch of a combination (include/sph.h: sph_batched_set_config)."""
+    if variant not in BATCHED_VARIANTS:
+        raise SphError(SPH_ERR_INVALID, f"unknown variant {variant!r}")
+    code = SPH_F64 if dtype == torch.float64 else SPH_F32
+    _check(lib().sph_batched_set_config(int(l_max), int(bool(normalize)), code, int(bool(store_dY)),
+                                        int(bool(with_backward)), BATCHED_VARIANTS[variant], int(blocks_per_cu)))

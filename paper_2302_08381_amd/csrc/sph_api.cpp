@@ -76,8 +76,10 @@ int32_t check_no_overlap(std::initializer_list<Range> outs, std::initializer_lis
 
 // The forward kernel for a set of outputs: values only (one lane per point)
 // unless dY is stored or the backward is fused (four lanes per point).
-sph::KernelInfo fwd_info(int32_t dtype, int L, int norm, bool store_dy, bool fused) {
-  using KF = sph::KernelInfo (*)(int);
+// variant: see sph::FwdVariant (fn == nullptr where it does not exist).
+sph::KernelInfo fwd_info(int32_t dtype, int L, int norm, bool store_dy, bool fused,
+                         int variant = sph::kVarDefault) {
+  using KF = sph::KernelInfo (*)(int, int);
   static constexpr KF kValues[2][2] = {{sph::fwd_values_f32_n0, sph::fwd_values_f32_n1},
                                        {sph::fwd_values_f64_n0, sph::fwd_values_f64_n1}};
   static constexpr KF kDerivs[2][2][sph::kNumDerivModes] = {
@@ -87,9 +89,9 @@ sph::KernelInfo fwd_info(int32_t dtype, int L, int norm, bool store_dy, bool fus
        {sph::fwd_derivs_f64_n1_m0, sph::fwd_derivs_f64_n1_m1, sph::fwd_derivs_f64_n1_m2}}};
   const int d = dtype == SPH_F64 ? 1 : 0;
   const int n = norm ? 1 : 0;
-  if (!store_dy && !fused) return kValues[d][n](L);
+  if (!store_dy && !fused) return kValues[d][n](L, variant);
   const int mode = !fused ? sph::kDerivStore : (store_dy ? sph::kDerivFusedStore : sph::kDerivFused);
-  return kDerivs[d][n][mode](L);
+  return kDerivs[d][n][mode](L, variant);
 }
 sph::KernelInfo bwd_info(int32_t dtype, int L) {
   return dtype == SPH_F64 ? sph::bwd_info_f64(L) : sph::bwd_info_f32(L);
@@ -150,11 +152,23 @@ struct BatchKey {
   }
 };
 
-// Persistent-grid size: blocks_per_cu * CUs blocks loop over the tiles;
-// 0 means one tile per block (a plain grid).
+// Kernel variant (sph::FwdVariant: unrolled with its default tile, unrolled
+// on a 16-point tile, or the run-time-degree kernel) and persistent-grid
+// size: blocks_per_cu * CUs blocks loop over the tiles; 0 means one tile per
+// block (a plain grid).
 struct Choice {
+  int variant = sph::kVarDefault;
   int blocks_per_cu = 8;
 };
+
+const char* variant_name(int v) {
+  switch (v) {
+    case sph::kVarDefault: return "default";
+    case sph::kVarTile16: return "tile16";
+    case sph::kVarRuntime: return "runtime_degree";
+    default: return "?";
+  }
+}
 
 struct GraphEntry {
   hipGraph_t graph = nullptr;
@@ -180,7 +194,7 @@ std::string cache_path() {
 }
 
 // Cache file: one line per combination,
-//   dtype L normalize store_dY backward blocks_per_cu
+//   dtype L normalize store_dY backward variant blocks_per_cu
 // Unreadable or malformed lines are ignored (defaults apply).
 void load_cache_locked() {
   if (g_cache_loaded) return;
@@ -191,12 +205,13 @@ void load_cache_locked() {
   std::string line;
   while (std::getline(f, line)) {
     std::istringstream is(line);
-    int dt, L, nm, sd, bw, b;
-    if (!(is >> dt >> L >> nm >> sd >> bw >> b)) continue;
+    int dt, L, nm, sd, bw, v, b;
+    if (!(is >> dt >> L >> nm >> sd >> bw >> v >> b)) continue;
     if (dt < 0 || dt > 1 || L < 0 || L > sph::kMaxLmax || nm < 0 || nm > 1 || sd < 0 || sd > 1 || bw < 0 ||
-        bw > 1 || b < 0 || b > 64)
+        bw > 1 || v < 0 || v >= sph::kNumFwdVariants || b < 0 || b > 64)
       continue;
-    for (int dev = 0; dev < 64; ++dev) g_choice[BatchKey{dev, dt, L, nm, sd, bw}] = Choice{b};
+    if (fwd_info(dt == 1 ? SPH_F64 : SPH_F32, L, nm, sd != 0, bw != 0, v).fn == nullptr) continue;
+    for (int dev = 0; dev < 64; ++dev) g_choice[BatchKey{dev, dt, L, nm, sd, bw}] = Choice{v, b};
   }
 }
 
@@ -208,7 +223,7 @@ void save_cache_locked() {
   for (const auto& kv : g_choice) {
     if (kv.first.dev != 0) continue;
     f << kv.first.dtype << ' ' << kv.first.L << ' ' << kv.first.norm << ' ' << kv.first.store_dy << ' '
-      << kv.first.bwd << ' ' << kv.second.blocks_per_cu << '\n';
+      << kv.first.bwd << ' ' << kv.second.variant << ' ' << kv.second.blocks_per_cu << '\n';
   }
 }
 
@@ -218,10 +233,12 @@ unsigned batched_grid(const sph::KernelInfo& ki, int64_t n, int bpc) {
   return static_cast<unsigned>(std::max<int64_t>(1, g));
 }
 
-// Times every persistent-grid size on the caller's buffers (the kernel is a
-// pure function of its inputs, so repeated runs leave the right result) and
-// returns the fastest.  Synchronises the host.
-Choice autotune(const sph::KernelInfo& ki, size_t lds, sph::FwdParams params, hipStream_t s) {
+// Times every kernel variant of the combination with every persistent-grid
+// size on the caller's buffers (the kernel is a pure function of its inputs,
+// so repeated runs leave the right result) and returns the fastest.
+// Synchronises the host.
+Choice autotune(int32_t dtype, int L, int norm, bool store_dy, bool fused, sph::FwdParams params,
+                hipStream_t s) {
   Choice best;
   float best_ms = 1e30f;
   hipEvent_t e0, e1;
@@ -230,21 +247,27 @@ Choice autotune(const sph::KernelInfo& ki, size_t lds, sph::FwdParams params, hi
     (void)hipEventDestroy(e0);
     return best;
   }
-  for (int bpc : kBpcCandidates) {
-    const unsigned grid = batched_grid(ki, params.n, bpc);
-    sph::FwdParams p = params;
-    if (launch(ki.fn, grid, ki.block, lds, &p, s) != hipSuccess) continue;  // warm-up
-    (void)hipEventRecord(e0, s);
-    constexpr int reps = 3;
-    bool okr = true;
-    for (int r = 0; r < reps && okr; ++r) okr = launch(ki.fn, grid, ki.block, lds, &p, s) == hipSuccess;
-    (void)hipEventRecord(e1, s);
-    if (!okr || hipEventSynchronize(e1) != hipSuccess) continue;
-    float ms = 0;
-    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) continue;
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = Choice{bpc};
+  for (int v = 0; v < sph::kNumFwdVariants; ++v) {
+    const sph::KernelInfo ki = fwd_info(dtype, L, norm, store_dy, fused, v);
+    if (ki.fn == nullptr) continue;
+    const size_t lds = fused ? ki.lds_bytes_bwd : ki.lds_bytes;
+    if (ensure_lds(ki.fn, lds) != hipSuccess) continue;
+    for (int bpc : kBpcCandidates) {
+      const unsigned grid = batched_grid(ki, params.n, bpc);
+      sph::FwdParams p = params;
+      if (launch(ki.fn, grid, ki.block, lds, &p, s) != hipSuccess) continue;  // warm-up
+      (void)hipEventRecord(e0, s);
+      constexpr int reps = 3;
+      bool okr = true;
+      for (int r = 0; r < reps && okr; ++r) okr = launch(ki.fn, grid, ki.block, lds, &p, s) == hipSuccess;
+      (void)hipEventRecord(e1, s);
+      if (!okr || hipEventSynchronize(e1) != hipSuccess) continue;
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) continue;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = Choice{v, bpc};
+      }
     }
   }
   (void)hipEventDestroy(e0);
@@ -378,9 +401,30 @@ int32_t sph_batched_get_config(int32_t l_max, int32_t normalize, int32_t dtype, 
   std::lock_guard<std::mutex> lk(g_batch_mu);
   auto it = g_choice.find(BatchKey{dev, dtype, l_max, normalize, store_dY ? 1 : 0, with_backward ? 1 : 0});
   if (it == g_choice.end()) return fail(SPH_ERR_INVALID, "no configuration chosen yet");
-  const sph::KernelInfo ki = fwd_info(dtype, l_max, normalize, store_dY != 0, with_backward != 0);
-  std::snprintf(buf, static_cast<size_t>(len), "blocks_per_cu=%d tile_points=%d", it->second.blocks_per_cu,
-                ki.tile_points);
+  const sph::KernelInfo ki =
+      fwd_info(dtype, l_max, normalize, store_dY != 0, with_backward != 0, it->second.variant);
+  std::snprintf(buf, static_cast<size_t>(len), "kernel=%s blocks_per_cu=%d tile_points=%d",
+                variant_name(it->second.variant), it->second.blocks_per_cu, ki.tile_points);
+  return ok();
+}
+
+int32_t sph_batched_set_config(int32_t l_max, int32_t normalize, int32_t dtype, int32_t store_dY,
+                               int32_t with_backward, int32_t variant, int32_t blocks_per_cu) {
+  int32_t st = check_common(0, l_max, dtype);
+  if (st != SPH_OK) return st;
+  if ((st = check_norm(normalize)) != SPH_OK) return st;
+  if ((store_dY != 0 && store_dY != 1) || (with_backward != 0 && with_backward != 1))
+    return fail(SPH_ERR_INVALID, "store_dY and with_backward must be 0 or 1");
+  if (variant < 0 || variant >= sph::kNumFwdVariants) return fail(SPH_ERR_INVALID, "unknown variant");
+  if (blocks_per_cu < 0 || blocks_per_cu > 64) return fail(SPH_ERR_INVALID, "blocks_per_cu must be in 0..64");
+  if (fwd_info(dtype, l_max, normalize, store_dY != 0, with_backward != 0, variant).fn == nullptr)
+    return fail(SPH_ERR_INVALID, "this variant does not exist for the combination");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  (void)hipGetLastError();
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  load_cache_locked();
+  g_choice[BatchKey{dev, dtype, l_max, normalize, store_dY, with_backward}] = Choice{variant, blocks_per_cu};
   return ok();
 }
 
@@ -419,11 +463,8 @@ int32_t sph_batched_compute(const void* xyz, const int64_t* offsets, int64_t n_e
   const BatchKey key{dev, dtype, l_max, normalize, dY != nullptr ? 1 : 0, bwd ? 1 : 0};
   sph::FwdParams p{xyz, n_points, l_max, Y, dY, grad_Y, grad_xyz, offsets, n_env, status};
 
-  const sph::KernelInfo ki = fwd_info(dtype, l_max, normalize, dY != nullptr, bwd);
-  if (ki.fn == nullptr) return fail(SPH_ERR_INVALID, "no kernel for these arguments");
-  const size_t lds = bwd ? ki.lds_bytes_bwd : ki.lds_bytes;
-  e = ensure_lds(ki.fn, lds);
-  if (e != hipSuccess) return device_fail(e, "hipFuncSetAttribute");
+  if (fwd_info(dtype, l_max, normalize, dY != nullptr, bwd).fn == nullptr)
+    return fail(SPH_ERR_INVALID, "no kernel for these arguments");
 
   std::lock_guard<std::mutex> lk(g_batch_mu);
   load_cache_locked();
@@ -432,12 +473,17 @@ int32_t sph_batched_compute(const void* xyz, const int64_t* offsets, int64_t n_e
   if (it != g_choice.end()) {
     ch = it->second;
   } else if (g_autotune && !capturing && n_points >= int64_t(64) * 256) {
-    ch = autotune(ki, lds, p, s);
+    ch = autotune(dtype, l_max, normalize, dY != nullptr, bwd, p, s);
     g_choice[key] = ch;
     save_cache_locked();
   } else {
     g_choice[key] = ch;
   }
+  const sph::KernelInfo ki = fwd_info(dtype, l_max, normalize, dY != nullptr, bwd, ch.variant);
+  if (ki.fn == nullptr) return fail(SPH_ERR_INVALID, "no kernel for the chosen variant");
+  const size_t lds = bwd ? ki.lds_bytes_bwd : ki.lds_bytes;
+  e = ensure_lds(ki.fn, lds);
+  if (e != hipSuccess) return device_fail(e, "hipFuncSetAttribute");
   const unsigned grid = batched_grid(ki, n_points, ch.blocks_per_cu);
 
   if (!g_use_graph || capturing) {

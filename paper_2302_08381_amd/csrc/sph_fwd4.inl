@@ -322,7 +322,8 @@ constexpr bool quad_has_fast() {
 }
 
 // LT >= 0: l_max = LT known at compile time (MM = LT, degree loops unrolled);
-// LT < 0: l_max = P.L <= MM at run time.  FUSED: the backward is fused
+// LT < 0: l_max = P.L <= MM at run time.  NW waves per block (a tile of
+// 16 NW points; quad_waves gives the default).  FUSED: the backward is fused
 // (P.gY, P.gxyz); STORE: dY is written.  Dynamic LDS: 4 PT rows of
 // stride(L) elements, plus PT rows for the upstream-gradient tile when FUSED.
 //
@@ -333,9 +334,8 @@ constexpr bool quad_has_fast() {
 // different numbers of memory operations would turn that wait into a drain
 // of every store of the tile, so the ragged last tile and unaligned outputs
 // take a separate general path.
-template <typename T, int MM, int LT, bool NORM, bool FUSED, bool STORE>
-__global__ __launch_bounds__(kWave * quad_waves<T>(LT)) void k_fwd4(FwdParams P) {
-  constexpr int NW = quad_waves<T>(LT);
+template <typename T, int MM, int LT, bool NORM, bool FUSED, bool STORE, int NW>
+__global__ __launch_bounds__(kWave * NW) void k_fwd4(FwdParams P) {
   constexpr int PT = kQuadWavePoints * NW;  // points per tile
   constexpr int NT = kWave * NW;            // threads per block
   constexpr int B = kQuadBudget<T>;

@@ -34,20 +34,36 @@ template <int MM, int LT>
 const void* kernel_ptr() {
   return reinterpret_cast<const void*>(&k_fwd<T, MM, LT, kNorm>);
 }
+template <int LT>
+const void* alt_ptr() {
+  return nullptr;
+}
 #else
 constexpr bool kFused = SPH_MODE != kDerivStore;
 constexpr bool kStore = SPH_MODE != kDerivFused;
 template <int MM, int LT>
 const void* kernel_ptr() {
-  return reinterpret_cast<const void*>(&k_fwd4<T, MM, LT, kNorm, kFused, kStore>);
+  return reinterpret_cast<const void*>(&k_fwd4<T, MM, LT, kNorm, kFused, kStore, quad_waves<T>(LT)>);
+}
+// The compile-time kernel on a one-wave tile where the default takes two.
+template <int LT>
+const void* alt_ptr() {
+  if constexpr (quad_waves<T>(LT) == 2)
+    return reinterpret_cast<const void*>(&k_fwd4<T, LT, LT, kNorm, kFused, kStore, 1>);
+  else
+    return nullptr;
 }
 #endif
 
 template <int... Ls>
-void fill_spec(const void** out, std::integer_sequence<int, Ls...>) {
+void fill_spec(const void** out, const void** alt, std::integer_sequence<int, Ls...>) {
   if constexpr (kSpecMax >= 0) {
     const void* v[] = {kernel_ptr<Ls, Ls>()...};
-    for (size_t i = 0; i < sizeof...(Ls); ++i) out[i] = v[i];
+    const void* a[] = {alt_ptr<Ls>()...};
+    for (size_t i = 0; i < sizeof...(Ls); ++i) {
+      out[i] = v[i];
+      alt[i] = a[i];
+    }
   }
 }
 
@@ -59,12 +75,14 @@ void fill_buckets(const void** out, std::integer_sequence<int, Is...>) {
 
 struct Tables {
   const void* spec[kSpecSlots] = {};
+  const void* spec_alt[kSpecSlots] = {};
   const void* buckets[kNumBuckets] = {};
   Tables() {
-    if constexpr (kSpecMax >= 0) fill_spec(spec, std::make_integer_sequence<int, kSpecSlots>{});
+    if constexpr (kSpecMax >= 0) fill_spec(spec, spec_alt, std::make_integer_sequence<int, kSpecSlots>{});
     fill_buckets(buckets, Buckets{});
   }
 };
+
 #else
 template <bool NORM, int... Is>
 void fill_dbwd(const void** out, std::integer_sequence<int, Is...>) {
@@ -89,21 +107,44 @@ const Tables& tables() {
   return t;
 }
 
+#if SPH_FAMILY == 1 || SPH_FAMILY == 3
+// Kernel of a variant (see FwdVariant) and its tile width in waves.
+const void* pick(int L, int variant, int& nw, bool quad) {
+  const bool ct = L <= kSpecMax;
+  nw = 1;
+  switch (variant) {
+    case kVarDefault:
+      if (ct && quad) nw = quad_waves<T>(L);
+      return ct ? tables().spec[L] : tables().buckets[bucket_index(L)];
+    case kVarTile16:
+      return ct ? tables().spec_alt[L] : nullptr;
+    case kVarRuntime:
+      return ct ? tables().buckets[bucket_index(L)] : nullptr;
+    default:
+      return nullptr;
+  }
+}
+#endif
+
 }  // namespace
 
 #if SPH_FAMILY == 1
-KernelInfo SPH_CAT(SPH_CAT(SPH_CAT(fwd_values_, SPH_SUFFIX), _n), SPH_NORM)(int L) {
+KernelInfo SPH_CAT(SPH_CAT(SPH_CAT(fwd_values_, SPH_SUFFIX), _n), SPH_NORM)(int L, int variant) {
   if (!in_range(L)) return KernelInfo{nullptr, 0, 0, 0, 0};
-  const void* fn = L <= kSpecMax ? tables().spec[L] : tables().buckets[bucket_index(L)];
+  int nw = 1;
+  const void* fn = pick(L, variant, nw, false);
+  if (fn == nullptr) return KernelInfo{nullptr, 0, 0, 0, 0};
   const size_t lds = sizeof(T) * kWave * static_cast<size_t>(plan_stride(L, kValueBudget<T>));
   return KernelInfo{fn, lds, lds, kWave, kWave};
 }
 #elif SPH_FAMILY == 3
-KernelInfo SPH_CAT(SPH_CAT(SPH_CAT(SPH_CAT(SPH_CAT(fwd_derivs_, SPH_SUFFIX), _n), SPH_NORM), _m), SPH_MODE)(int L) {
+KernelInfo SPH_CAT(SPH_CAT(SPH_CAT(SPH_CAT(SPH_CAT(fwd_derivs_, SPH_SUFFIX), _n), SPH_NORM), _m), SPH_MODE)(
+    int L, int variant) {
   if (!in_range(L)) return KernelInfo{nullptr, 0, 0, 0, 0};
-  const void* fn = L <= kSpecMax ? tables().spec[L] : tables().buckets[bucket_index(L)];
+  int nw = 1;
+  const void* fn = pick(L, variant, nw, true);
+  if (fn == nullptr) return KernelInfo{nullptr, 0, 0, 0, 0};
   const size_t row = sizeof(T) * static_cast<size_t>(plan_stride(L, kQuadBudget<T>));
-  const int nw = quad_waves<T>(L <= kSpecMax ? L : -1);  // as the kernel's own tile
   const int pts = kQuadWavePoints * nw, thr = kWave * nw;
   return KernelInfo{fn, row * static_cast<size_t>(4 * pts), row * static_cast<size_t>(5 * pts), pts, thr};
 }

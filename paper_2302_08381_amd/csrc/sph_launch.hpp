@@ -57,28 +57,36 @@ struct KernelInfo {
 };
 
 // Per element type (suffix f32 / f64) and normalisation; fn == nullptr when
-// the arguments are out of range.
+// the arguments are out of range or the variant does not exist for l_max.
 //   values:      Y only (one lane per point, 64-point tiles, 64 threads)
-//   derivatives: four lanes per point, 32-point tiles, 128 threads; mode
+//   derivatives: four lanes per point, 32- or 16-point tiles; mode
 //                kDerivStore (Y and dY), kDerivFusedStore (Y, dY and the
 //                fused backward), kDerivFused (Y and the fused backward)
+// Variants (the batched autotuner's candidates):
+//   kVarDefault  the compile-time (unrolled) kernel where one exists, with its
+//                default tile, else the run-time-degree kernel
+//   kVarTile16   the compile-time kernel on a 16-point, one-wave tile where
+//                the default tile is 32 points (float, l_max <= 8)
+//   kVarRuntime  the run-time-degree (not unrolled) kernel where the default
+//                is a compile-time one
 enum DerivMode { kDerivStore = 0, kDerivFusedStore = 1, kDerivFused = 2, kNumDerivModes = 3 };
-KernelInfo fwd_values_f32_n0(int L);
-KernelInfo fwd_values_f32_n1(int L);
-KernelInfo fwd_values_f64_n0(int L);
-KernelInfo fwd_values_f64_n1(int L);
-KernelInfo fwd_derivs_f32_n0_m0(int L);
-KernelInfo fwd_derivs_f32_n0_m1(int L);
-KernelInfo fwd_derivs_f32_n0_m2(int L);
-KernelInfo fwd_derivs_f32_n1_m0(int L);
-KernelInfo fwd_derivs_f32_n1_m1(int L);
-KernelInfo fwd_derivs_f32_n1_m2(int L);
-KernelInfo fwd_derivs_f64_n0_m0(int L);
-KernelInfo fwd_derivs_f64_n0_m1(int L);
-KernelInfo fwd_derivs_f64_n0_m2(int L);
-KernelInfo fwd_derivs_f64_n1_m0(int L);
-KernelInfo fwd_derivs_f64_n1_m1(int L);
-KernelInfo fwd_derivs_f64_n1_m2(int L);
+enum FwdVariant { kVarDefault = 0, kVarTile16 = 1, kVarRuntime = 2, kNumFwdVariants = 3 };
+KernelInfo fwd_values_f32_n0(int L, int variant);
+KernelInfo fwd_values_f32_n1(int L, int variant);
+KernelInfo fwd_values_f64_n0(int L, int variant);
+KernelInfo fwd_values_f64_n1(int L, int variant);
+KernelInfo fwd_derivs_f32_n0_m0(int L, int variant);
+KernelInfo fwd_derivs_f32_n0_m1(int L, int variant);
+KernelInfo fwd_derivs_f32_n0_m2(int L, int variant);
+KernelInfo fwd_derivs_f32_n1_m0(int L, int variant);
+KernelInfo fwd_derivs_f32_n1_m1(int L, int variant);
+KernelInfo fwd_derivs_f32_n1_m2(int L, int variant);
+KernelInfo fwd_derivs_f64_n0_m0(int L, int variant);
+KernelInfo fwd_derivs_f64_n0_m1(int L, int variant);
+KernelInfo fwd_derivs_f64_n0_m2(int L, int variant);
+KernelInfo fwd_derivs_f64_n1_m0(int L, int variant);
+KernelInfo fwd_derivs_f64_n1_m1(int L, int variant);
+KernelInfo fwd_derivs_f64_n1_m2(int L, int variant);
 KernelInfo bwd_info_f32(int L);
 KernelInfo bwd_info_f64(int L);
 KernelInfo dbwd_info_f32(int L, int normalize);

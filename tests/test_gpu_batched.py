@@ -8,7 +8,7 @@ import torch
 import oracle
 from workloads import SEEDS, csr_environments, standard_normal
 
-from _gpu_common import TOL, assert_bitwise_equal, host_points, to_dev
+from _gpu_common import TOL, assert_bitwise_equal, assert_close_per_l, host_points, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -26,6 +26,8 @@ def test_batched_equals_plain_and_oracle(l_max):
     xyz = to_dev(pts, torch.float32)
     gY = to_dev(standard_normal((n, K), 70 + l_max), torch.float32)
     status = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    # the plain call's kernel (the run-time-degree variant rounds differently)
+    sph.sph_batched_set_config(l_max, True, torch.float32, True, True, "default", 0)
     out = sph.sph_batched_compute(xyz, _offsets(offs), l_max, True, store_dY=True, grad_Y=gY, status=status)
     Y, dY = sph.sph_compute_with_gradients(xyz, l_max, True)
     gx = sph.sph_backward(dY, gY, l_max)
@@ -141,7 +143,7 @@ def test_batched_workload_autotuned_per_lmax():
         torch.cuda.synchronize()
         assert int(st.item()) == 0
         cfg = sph.sph_batched_get_config(L, True, torch.float32, True, True)
-        assert cfg is not None and "blocks_per_cu=" in cfg
+        assert cfg is not None and "blocks_per_cu=" in cfg and "kernel=" in cfg
         idx = torch.arange(0, n, 1999, device="cuda")
         hp = host_points(xyz[idx])
         Yr, Gr = oracle.real_sph(hp, L, True)
@@ -149,3 +151,43 @@ def test_batched_workload_autotuned_per_lmax():
         assert mx.max() <= TOL[torch.float32]
         mx, _ = oracle.per_l_errors(out["dY"][idx].cpu().numpy(), Gr, hp, L, True, "dY")
         assert mx.max() <= TOL[torch.float32]
+
+
+@pytest.mark.parametrize("l_max", [3, 8, 12])
+def test_every_batched_variant_matches_oracle(l_max):
+    """Each kernel variant the autotuner can pick (unrolled on its default
+    tile, unrolled on a 16-point tile, run-time degree), pinned with
+    sph_batched_set_config, on a one-tile-per-block and a persistent grid."""
+    import paper_2302_08381_amd as sph
+    pts, offs = csr_environments(300, 8, 128, 0.5, 5.0, SEEDS["batched"] + l_max)
+    n = int(offs[-1])
+    K = (l_max + 1) ** 2
+    xyz = to_dev(pts, torch.float32)
+    o = _offsets(offs)
+    gY = to_dev(standard_normal((n, K), 2000 + l_max), torch.float32)
+    hp = host_points(xyz)
+    Yr, Gr = oracle.real_sph(hp, l_max, True)
+    gYh = gY.cpu().double().numpy()
+    gref = np.asarray(oracle.backward(Gr, gYh), float)
+    _, gsc, _ = oracle.component_scales(hp, l_max, True)
+    gscale = (np.abs(gYh) * gsc).sum(1)[:, None]
+    ran = []
+    for variant in ("default", "tile16", "runtime_degree"):
+        for bpc in (0, 4):
+            print(f"batched variant l_max={l_max} {variant} bpc={bpc}", flush=True)
+            try:
+                sph.sph_batched_set_config(l_max, True, torch.float32, True, True, variant, bpc)
+            except sph.SphError:
+                assert variant == "tile16" and l_max > 8
+                continue
+            cfg = sph.sph_batched_get_config(l_max, True, torch.float32, True, True)
+            assert f"kernel={variant}" in cfg and f"blocks_per_cu={bpc}" in cfg
+            out = sph.sph_batched_compute(xyz, o, l_max, True, store_dY=True, grad_Y=gY)
+            torch.cuda.synchronize()
+            assert_close_per_l(out["Y"].cpu().numpy(), Yr, hp, l_max, True, "Y", TOL[torch.float32], variant)
+            assert_close_per_l(out["dY"].cpu().numpy(), Gr, hp, l_max, True, "dY", TOL[torch.float32], variant)
+            err = np.abs(out["grad_xyz"].cpu().double().numpy() - gref) / gscale
+            assert err.max() <= TOL[torch.float32], (variant, bpc, err.max())
+            ran.append(variant)
+    assert "default" in ran and "runtime_degree" in ran
+    sph.sph_batched_set_config(l_max, True, torch.float32, True, True, "default", 0)
