@@ -30,6 +30,7 @@ constexpr int bwd_waves(int K) {
   return (std::is_same_v<T, float> && K <= bwd_chunk<T, 2>()) ? 2 : 1;
 }
 constexpr int kBwdBatch = 16;
+constexpr int kBwdPairBatch = 32;
 
 template <typename T, int NW>
 __global__ __launch_bounds__(kWave * NW) void k_bwd(BwdParams P) {
@@ -55,8 +56,13 @@ __global__ __launch_bounds__(kWave * NW) void k_bwd(BwdParams P) {
   for (int kc0 = 0; kc0 < K; kc0 += ch) {
     const int cnt = (K - kc0) < ch ? (K - kc0) : ch;
     const int S = cnt | 1;
-    copy_in<NT, kBwdBatch>(sg, S, gY + kc0, K, cnt, np, lane, aligned16(gY + kc0));
-    copy_in<NT, kBwdBatch>(sd, S, dY + kc0, K, cnt, 3 * np, lane, aligned16(dY + kc0));
+    if (cnt == K && S == K && aligned16(gY) && aligned16(dY)) {
+      // one chunk of whole rows: the gY and dY blocks share the round trips
+      copy_in_pair<NT, kBwdPairBatch>(sg, gY, np * K, sd, dY, 3 * np * K, lane);
+    } else {
+      copy_in<NT, kBwdBatch>(sg, S, gY + kc0, K, cnt, np, lane, aligned16(gY + kc0));
+      copy_in<NT, kBwdBatch>(sd, S, dY + kc0, K, cnt, 3 * np, lane, aligned16(dY + kc0));
+    }
     __syncthreads();
     if (pl < np) {
       const T* g = sg + pl * S;

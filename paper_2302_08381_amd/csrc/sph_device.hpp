@@ -382,6 +382,38 @@ __device__ __forceinline__ void copy_in(T* __restrict__ st, int S, const T* __re
   }
 }
 
+// Two contiguous global blocks a[0, na) and b[0, nb) (16-byte aligned) into
+// two LDS blocks, as one list of 16-byte vectors with NB per thread in flight:
+// both blocks share the memory round trips.  Elements past the last whole
+// vector of each block are copied one by one.
+template <int NT, int NB, typename T>
+__device__ __forceinline__ void copy_in_pair(T* __restrict__ sa, const T* __restrict__ a, int na,
+                                             T* __restrict__ sb, const T* __restrict__ b, int nb, int lane) {
+  using V = typename Vec16<T>::type;
+  constexpr int W = Vec16<T>::n;
+  const int nva = na / W, nvb = nb / W;
+  const int nv = nva + nvb;
+  const V* ga = reinterpret_cast<const V*>(a);
+  const V* gb = reinterpret_cast<const V*>(b);
+  V* la = reinterpret_cast<V*>(sa);
+  V* lb = reinterpret_cast<V*>(sb);
+  for (int i0 = lane; i0 < nv; i0 += NT * NB) {
+    V v[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int i = i0 + u * NT;
+      if (i < nv) v[u] = __builtin_nontemporal_load(i < nva ? ga + i : gb + (i - nva));
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int i = i0 + u * NT;
+      if (i < nv) *(i < nva ? la + i : lb + (i - nva)) = v[u];
+    }
+  }
+  for (int j = nva * W + lane; j < na; j += NT) sa[j] = __builtin_nontemporal_load(a + j);
+  for (int j = nvb * W + lane; j < nb; j += NT) sb[j] = __builtin_nontemporal_load(b + j);
+}
+
 // Full-tile contiguous copy with compile-time size: NV 16-byte vectors from
 // LDS to global by NT threads, kBatchFull in flight per lane, no predication
 // except on the last, partial sweep.
