@@ -55,6 +55,25 @@ struct Vec16<double> {
   static constexpr int n = 2;
 };
 
+// Streaming 16-byte stores of whole output tiles: a buffer store with the
+// system-scope (sc1) and nontemporal (nt) cache-policy bits.  On MI355X it
+// writes the forward's tiles 2-4 % faster than a plain nontemporal store
+// (float and double Y+dY, values only), and the default policy is slower
+// still.  The buffer resource covers [base, base + bytes); the hardware drops
+// any store past its end.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kStreamStorePolicy = 16 | 2;  // sc1 | nt
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t stream_rsrc(void* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(base, 0, bytes, 0x00020000);
+}
+
+template <typename V>
+__device__ __forceinline__ void stream_store16(const V& v, __amdgpu_buffer_rsrc_t rs, int byte_off) {
+  static_assert(sizeof(V) == 16, "16-byte vector");
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rs, byte_off, 0, kStreamStorePolicy);
+}
+
 // ------------------------------------------------------------ group plans
 // Consecutive degrees are grouped so that one component of one group fits
 // the per-point LDS budget (in elements).  A single degree larger than the
@@ -299,7 +318,7 @@ __device__ __forceinline__ void copy_out(const T* __restrict__ st, int S, T* __r
     constexpr int W = Vec16<T>::n;
     const int nv = total / W;
     const V* sv = reinterpret_cast<const V*>(st);
-    V* dv = reinterpret_cast<V*>(dst);
+    const __amdgpu_buffer_rsrc_t rs = stream_rsrc(dst, nv * 16);
     for (int i0 = lane; i0 < nv; i0 += NT * NB) {
       V v[NB];
 #pragma unroll
@@ -307,7 +326,7 @@ __device__ __forceinline__ void copy_out(const T* __restrict__ st, int S, T* __r
         if (i0 + u * NT < nv) v[u] = sv[i0 + u * NT];
 #pragma unroll
       for (int u = 0; u < NB; ++u)
-        if (i0 + u * NT < nv) __builtin_nontemporal_store(v[u], dv + i0 + u * NT);
+        if (i0 + u * NT < nv) stream_store16(v[u], rs, (i0 + u * NT) * 16);
     }
     for (int j = nv * W + lane; j < total; j += NT) __builtin_nontemporal_store(st[j], dst + j);
     return;
@@ -423,7 +442,7 @@ template <typename T, int NV, int NT = kWave>
 __device__ __forceinline__ void copy_out_full(const T* __restrict__ st, T* __restrict__ dst, int lane) {
   using V = typename Vec16<T>::type;
   const V* sv = reinterpret_cast<const V*>(st);
-  V* dv = reinterpret_cast<V*>(dst);
+  const __amdgpu_buffer_rsrc_t rs = stream_rsrc(dst, NV * 16);
   constexpr int kSweeps = (NV + NT - 1) / NT;
 #pragma unroll
   for (int s0 = 0; s0 < kSweeps; s0 += kBatchFull) {
@@ -437,7 +456,7 @@ __device__ __forceinline__ void copy_out_full(const T* __restrict__ st, T* __res
     for (int u = 0; u < kBatchFull; ++u) {
       const int sw = s0 + u;
       if (sw < kSweeps && (sw < NV / NT || lane + sw * NT < NV))
-        __builtin_nontemporal_store(v[u], dv + lane + sw * NT);
+        stream_store16(v[u], rs, (lane + sw * NT) * 16);
     }
   }
 }
