@@ -30,7 +30,11 @@ constexpr int bwd_waves(int K) {
   return (std::is_same_v<T, float> && K <= bwd_chunk<T, 2>()) ? 2 : 1;
 }
 constexpr int kBwdBatch = 16;
-constexpr int kBwdPairBatch = 32;
+// Loads in flight per thread for a one-chunk tile (gY and dY together):
+// measured best at 32 for float (two-wave blocks) and 48 for double (one-wave
+// blocks, 40.5 vectors per thread at l_max = 8); other depths are slower.
+template <typename T>
+inline constexpr int kBwdPairBatch = std::is_same_v<T, float> ? 32 : 48;
 
 template <typename T, int NW>
 __global__ __launch_bounds__(kWave * NW) void k_bwd(BwdParams P) {
@@ -44,6 +48,7 @@ __global__ __launch_bounds__(kWave * NW) void k_bwd(BwdParams P) {
   const int lane = threadIdx.x;
   const int pl = lane >> 2;
   const int q = lane & 3;
+  // plain block order: the XCD-contiguous order of the forward reads slower here
   const int64_t p0 = static_cast<int64_t>(blockIdx.x) * PP;
   if (p0 >= P.n) return;
   const int np = static_cast<int>(P.n - p0 < PP ? P.n - p0 : PP);
@@ -58,7 +63,7 @@ __global__ __launch_bounds__(kWave * NW) void k_bwd(BwdParams P) {
     const int S = cnt | 1;
     if (cnt == K && S == K && aligned16(gY) && aligned16(dY)) {
       // one chunk of whole rows: the gY and dY blocks share the round trips
-      copy_in_pair<NT, kBwdPairBatch>(sg, gY, np * K, sd, dY, 3 * np * K, lane);
+      copy_in_pair<NT, kBwdPairBatch<T>>(sg, gY, np * K, sd, dY, 3 * np * K, lane);
     } else {
       copy_in<NT, kBwdBatch>(sg, S, gY + kc0, K, cnt, np, lane, aligned16(gY + kc0));
       copy_in<NT, kBwdBatch>(sd, S, dY + kc0, K, cnt, 3 * np, lane, aligned16(dY + kc0));

@@ -461,6 +461,21 @@ __device__ __forceinline__ void copy_out_full(const T* __restrict__ st, T* __res
   }
 }
 
+// Block index -> tile slot, a permutation of [0, G) that gives the blocks
+// dispatched to one XCD (workgroups go to the 8 XCDs round-robin) one
+// contiguous range of slots, so each XCD writes one long run of output
+// instead of every eighth tile.  Correct for any dispatch order.  Measured on
+// the forward with derivatives at l_max = 8: 231.6 -> 208.0 us (float),
+// 446 -> 438 us (double); values only 58.0 -> 56.9 us.  The backward, which
+// reads, is 2 % slower in this order and keeps the plain one.
+constexpr int kNumXcd = 8;
+
+__device__ __forceinline__ int64_t xcd_slot(int64_t b, int64_t G) {
+  const int64_t x = b % kNumXcd, j = b / kNumXcd;
+  const int64_t q = G / kNumXcd, rem = G % kNumXcd;
+  return x * q + (x < rem ? x : rem) + j;
+}
+
 __device__ __forceinline__ bool aligned16(const void* p) {
   return (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
 }

@@ -130,25 +130,26 @@ __global__ __launch_bounds__(kWave) void k_fwd(FwdParams P) {
   };
 
   constexpr bool kFast = values_has_fast<T, LT>();
+  const int64_t slot = xcd_slot(blockIdx.x, gridDim.x);  // first tile of this block
   if (kFast && aligned16(P.Y)) {
     const int64_t nfull = P.n / kWave;
-    if (static_cast<int64_t>(blockIdx.x) < nfull) {
+    if (slot < nfull) {
       T nx, ny, nz;
-      load_point(blockIdx.x * kWave + lane, nx, ny, nz);
-      for (int64_t tile = blockIdx.x; tile < nfull; tile += gridDim.x) {
+      load_point(slot * kWave + lane, nx, ny, nz);
+      for (int64_t tile = slot; tile < nfull; tile += gridDim.x) {
         const T x = nx, y = ny, z = nz;
         const int64_t nt = tile + gridDim.x < nfull ? tile + gridDim.x : tile;
         load_point(nt * kWave + lane, nx, ny, nz);
         tile_body(tile, x, y, z, std::integral_constant<bool, kFast>{});
       }
     }
-    if (P.n % kWave != 0 && nfull % gridDim.x == blockIdx.x) {
+    if (P.n % kWave != 0 && nfull % gridDim.x == slot) {
       T x = T(0), y = T(0), z = T(0);
       if (nfull * kWave + lane < P.n) load_point(nfull * kWave + lane, x, y, z);
       tile_body(nfull, x, y, z, std::false_type{});
     }
   } else {
-    for (int64_t tile = blockIdx.x; tile * kWave < P.n; tile += gridDim.x) {
+    for (int64_t tile = slot; tile * kWave < P.n; tile += gridDim.x) {
       T x = T(0), y = T(0), z = T(0);
       if (tile * kWave + lane < P.n) load_point(tile * kWave + lane, x, y, z);
       tile_body(tile, x, y, z, std::false_type{});

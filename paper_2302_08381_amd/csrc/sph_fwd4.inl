@@ -384,12 +384,13 @@ __global__ __launch_bounds__(kWave * NW) void k_fwd4(FwdParams P) {
 
   constexpr bool kFast = quad_has_fast<T, LT>();
   const bool aligned = aligned16(P.Y) && (!STORE || aligned16(P.dY));
+  const int64_t slot = xcd_slot(blockIdx.x, gridDim.x);  // first tile of this block
   if (kFast && aligned) {
     const int64_t nfull = P.n / PT;
-    if (static_cast<int64_t>(blockIdx.x) < nfull) {
+    if (slot < nfull) {
       T nx, ny, nz;
-      load_point(blockIdx.x * PT + p, nx, ny, nz);
-      for (int64_t tile = blockIdx.x; tile < nfull; tile += gridDim.x) {
+      load_point(slot * PT + p, nx, ny, nz);
+      for (int64_t tile = slot; tile < nfull; tile += gridDim.x) {
         const T x = nx, y = ny, z = nz;
         // next full tile (clamped, so the load is unconditional)
         const int64_t nt = tile + gridDim.x < nfull ? tile + gridDim.x : tile;
@@ -397,13 +398,13 @@ __global__ __launch_bounds__(kWave * NW) void k_fwd4(FwdParams P) {
         tile_body(tile, x, y, z, std::integral_constant<bool, kFast>{});
       }
     }
-    if (P.n % PT != 0 && nfull % gridDim.x == blockIdx.x) {
+    if (P.n % PT != 0 && nfull % gridDim.x == slot) {
       T x = T(0), y = T(0), z = T(0);
       if (nfull * PT + p < P.n) load_point(nfull * PT + p, x, y, z);
       tile_body(nfull, x, y, z, std::false_type{});
     }
   } else {
-    for (int64_t tile = blockIdx.x; tile * PT < P.n; tile += gridDim.x) {
+    for (int64_t tile = slot; tile * PT < P.n; tile += gridDim.x) {
       T x = T(0), y = T(0), z = T(0);
       if (tile * PT + p < P.n) load_point(tile * PT + p, x, y, z);
       tile_body(tile, x, y, z, std::false_type{});

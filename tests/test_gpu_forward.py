@@ -148,3 +148,28 @@ def test_precision_stress_l32(dtype):
         assert mx.max() <= TOL[dtype], (c, mx)
         mx, _ = oracle.per_l_errors(dYc[m], Gr[m], hp[m], 32, True, "dY")
         assert mx.max() <= TOL[dtype], (c, mx)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_every_tile_written_for_grids_of_any_size(dtype):
+    """Blocks take tiles in an XCD-contiguous order (a permutation of the
+    grid): grids of 9..41 tiles with every remainder mod 8, full and ragged,
+    must still write every row."""
+    import paper_2302_08381_amd as sph
+    tile = 32 if dtype == torch.float32 else 16
+    for tiles, tail in ((9, 0), (10, 5), (13, 0), (19, 7), (24, 0), (31, 1), (41, 11)):
+        n = tiles * tile + tail
+        print(f"grid tiles={tiles} tail={tail} n={n} dtype={dtype}", flush=True)
+        pts = standard_normal_points(n, 500 + n)
+        xyz = to_dev(pts, dtype)
+        Y = torch.full((n, 81), float("nan"), dtype=dtype, device="cuda")
+        dY = torch.full((n, 3, 81), float("nan"), dtype=dtype, device="cuda")
+        sph.sph_compute_with_gradients(xyz, 8, True, Y=Y, dY=dY)
+        Yv = torch.full((n, 81), float("nan"), dtype=dtype, device="cuda")
+        sph.sph_compute(xyz, 8, True, Y=Yv)
+        torch.cuda.synchronize()
+        hp = host_points(xyz)
+        Yr, Gr = oracle.real_sph(hp, 8, True)
+        assert_close_per_l(Y.cpu().numpy(), Yr, hp, 8, True, "Y", TOL[dtype])
+        assert_close_per_l(dY.cpu().numpy(), Gr, hp, 8, True, "dY", TOL[dtype])
+        assert_close_per_l(Yv.cpu().numpy(), Yr, hp, 8, True, "Y", TOL[dtype])
