@@ -48,6 +48,39 @@ __device__ __forceinline__ void dbwd_group(const Point<T>& pt, T vx, T vy, T vz,
   const T ex = pt.ex, ey = pt.ey, ez = pt.ez;
   const T rho = ex * vx + ey * vy;
   const T uv = rho + ez * vz;  // u.v (normalised: ex = u)
+  // Terms of order m that do not depend on the degree, tabulated once per
+  // point for buckets up to m = 12 (a few dozen registers):
+  //   c_m, s_m;  m c_{m-1}, m s_{m-1} (gradients of c_m, s_m);
+  //   tv = grad(c_m).v, grad(s_m).v;  hA, hB with H(c_m) v = (hA, -hB),
+  //   H(s_m) v = (hB, hA)  (m(m-1) times the rotated (c_{m-2}, s_{m-2})).
+  constexpr bool kTab = MM <= 12;
+  constexpr int MT = kTab ? MM + 1 : 1;
+  T tc[MT], ts[MT], tmc[MT], tms[MT], tvc[MT], tvs[MT], thA[MT], thB[MT];
+  if constexpr (kTab) {
+    T s2 = T(0), c2 = T(0), s1 = T(0), c1 = T(1), s0 = T(0), c0 = T(1);
+#pragma unroll
+    for (int m = 0; m <= MM; ++m) {
+      if (m > 0) {
+        const T sn = ex * s0 + ey * c0;
+        const T cn = ex * c0 - ey * s0;
+        s2 = s1;
+        c2 = c1;
+        s1 = s0;
+        c1 = c0;
+        s0 = sn;
+        c0 = cn;
+      }
+      const T fm = T(m), fmm = T(m * (m - 1));
+      tc[m] = c0;
+      ts[m] = s0;
+      tmc[m] = fm * c1;
+      tms[m] = fm * s1;
+      tvc[m] = tmc[m] * vx - tms[m] * vy;
+      tvs[m] = tms[m] * vx + tmc[m] * vy;
+      thA[m] = fmm * (c2 * vx - s2 * vy);
+      thB[m] = fmm * (s2 * vx + c2 * vy);
+    }
+  }
   T pp[MM + 3], prev[MM + 3], cur[MM + 3];
   q_row_rt<T, MM>(la - 2, ez, pt.rxy2, pp);
   q_row_rt<T, MM>(la - 1, ez, pt.rxy2, prev);
@@ -81,7 +114,7 @@ __device__ __forceinline__ void dbwd_group(const Point<T>& pt, T vx, T vy, T vz,
 #pragma unroll
     for (int m = 0; m <= MM; ++m) {
       if (m > l) continue;  // no early exit: keeps the loop fully unrolled
-      if (m > 0) {
+      if (!kTab && m > 0) {
         const T sn = ex * s0 + ey * c0;
         const T cn = ex * c0 - ey * s0;
         s2 = s1;
@@ -106,6 +139,32 @@ __device__ __forceinline__ void dbwd_group(const Point<T>& pt, T vx, T vy, T vz,
       if (m == 0) {
         process(k0, q * kIS2, Qx * kIS2, Qy * kIS2, Cz * kIS2, gQv * kIS2, Hx * kIS2,
                 Hy * kIS2, Hz * kIS2);
+      } else if constexpr (kTab) {
+        const int mt = kTab ? m : 0;
+        const T c = tc[mt], sm = ts[mt], mc = tmc[mt], ms = tms[mt];
+        const T hA = thA[mt], hB = thB[mt];
+        {  // +m: t = c_m, grad t = (mc, -ms), H(t) v = (hA, -hB)
+          const T tv = tvc[mt];
+          const T gx = c * Qx + q * mc;
+          const T gy = c * Qy - q * ms;
+          const T gz = c * Cz;
+          const T gv = c * gQv + q * tv;
+          const T hx = c * Hx + Qx * tv + mc * gQv + q * hA;
+          const T hy = c * Hy + Qy * tv - ms * gQv - q * hB;
+          const T hz = c * Hz + Cz * tv;
+          process(k0 + m, q * c, gx, gy, gz, gv, hx, hy, hz);
+        }
+        {  // -m: t = s_m, grad t = (ms, mc), H(t) v = (hB, hA)
+          const T tv = tvs[mt];
+          const T gx = sm * Qx + q * ms;
+          const T gy = sm * Qy + q * mc;
+          const T gz = sm * Cz;
+          const T gv = sm * gQv + q * tv;
+          const T hx = sm * Hx + Qx * tv + ms * gQv + q * hB;
+          const T hy = sm * Hy + Qy * tv + mc * gQv + q * hA;
+          const T hz = sm * Hz + Cz * tv;
+          process(k0 - m, q * sm, gx, gy, gz, gv, hx, hy, hz);
+        }
       } else {
         const T fm = T(m);
         const T fmm = T(m * (m - 1));
