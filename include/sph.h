@@ -140,7 +140,8 @@ int32_t sph_double_backward(const void* xyz, const void* grad_Y, const void* v,
  * caller's own buffers and keeps the fastest; the timing synchronises the
  * host once.  The candidates are every kernel variant (the unrolled
  * compile-time kernel on its default tile, the same on a 16-point tile, the
- * run-time-degree kernel) crossed with every persistent-grid size.
+ * run-time-degree kernel, the 16-point tile with its degrees split between
+ * two waves) crossed with every persistent-grid size.
  *   xyz        in  [n_points,3]
  *   offsets    in  int64 [n_env+1], DEVICE memory
  *   n_env      number of environments (>= 0)
@@ -172,7 +173,7 @@ int32_t sph_batched_set_options(int32_t use_graph, int32_t autotune);
 /*
  * sph_batched_get_config -- the launch chosen for a combination, as
  * "kernel=<v> blocks_per_cu=<b> tile_points=<t>" in buf (NUL-terminated, at
- * most len bytes).  v is default, tile16 or runtime_degree;
+ * most len bytes).  v is default, tile16, runtime_degree or degree_split;
  * blocks_per_cu = 0 means one tile per block.  Returns SPH_ERR_INVALID if
  * nothing was chosen yet.
  */
@@ -184,13 +185,15 @@ int32_t sph_batched_get_config(int32_t l_max, int32_t normalize, int32_t dtype,
  * sph_batched_set_config -- fixes the launch of a combination instead of
  * timing the candidates (for callers that need a known launch, e.g. before
  * capturing a graph, and for testing every variant).
- *   variant        0 default, 1 tile16, 2 runtime_degree (as in
- *                  sph_batched_get_config)
+ *   variant        0 default, 1 tile16, 2 runtime_degree, 3 degree_split
+ *                  (as in sph_batched_get_config)
  *   blocks_per_cu  0 .. 64 (0: one tile per block)
  * Returns SPH_ERR_INVALID for an unknown combination, a variant that does
- * not exist for it (tile16 exists only for float, l_max <= 8 with dY or the
- * backward; runtime_degree only where the default is unrolled) or an out of
- * range blocks_per_cu; SPH_ERR_LMAX for l_max out of range.
+ * not exist for it, or an out of range blocks_per_cu; SPH_ERR_LMAX for l_max
+ * out of range.  With dY or the backward, tile16 and runtime_degree exist
+ * wherever the default is unrolled (float l_max <= 12, double l_max <= 8)
+ * and degree_split for float 9 <= l_max <= 12 and double 4 <= l_max <= 8;
+ * a variant may name the default kernel.  Values only: runtime_degree only.
  */
 int32_t sph_batched_set_config(int32_t l_max, int32_t normalize, int32_t dtype,
                                int32_t store_dY, int32_t with_backward,

@@ -166,6 +166,7 @@ const char* variant_name(int v) {
     case sph::kVarDefault: return "default";
     case sph::kVarTile16: return "tile16";
     case sph::kVarRuntime: return "runtime_degree";
+    case sph::kVarSplit: return "degree_split";
     default: return "?";
   }
 }
@@ -247,9 +248,14 @@ Choice autotune(int32_t dtype, int L, int norm, bool store_dy, bool fused, sph::
     (void)hipEventDestroy(e0);
     return best;
   }
+  const void* tried[sph::kNumFwdVariants] = {};
   for (int v = 0; v < sph::kNumFwdVariants; ++v) {
     const sph::KernelInfo ki = fwd_info(dtype, L, norm, store_dy, fused, v);
     if (ki.fn == nullptr) continue;
+    bool seen = false;  // two variants may name one kernel
+    for (int u = 0; u < v; ++u) seen = seen || tried[u] == ki.fn;
+    tried[v] = ki.fn;
+    if (seen) continue;
     const size_t lds = fused ? ki.lds_bytes_bwd : ki.lds_bytes;
     if (ensure_lds(ki.fn, lds) != hipSuccess) continue;
     for (int bpc : kBpcCandidates) {

@@ -308,6 +308,75 @@ __device__ __forceinline__ void fwd4_groups_ct(std::integer_sequence<int, Gs...>
    ...);
 }
 
+// Degree at which a one-group tile of compile-time l_max LT is split between
+// two waves: the l with l^2 (columns below it) closest to K/2.
+template <int LT>
+constexpr int split_degree() {
+  constexpr int K = (LT + 1) * (LT + 1);
+  int best = 1;
+  for (int l = 1; l <= LT; ++l) {
+    const int d = 2 * l * l - K, db = 2 * best * best - K;
+    if ((d < 0 ? -d : d) < (db < 0 ? -db : db)) best = l;
+  }
+  return best;
+}
+
+// A one-group 16-point tile whose degrees are split between the block's two
+// waves: wave 0 emits degrees [0, LS) and wave 1 degrees [LS, LT] of every
+// point (the branch is uniform per wave), both store the tile.  Twice the
+// waves of a one-wave tile on the same LDS, for kernels whose tile takes
+// most of a CU's LDS.  tid: thread of the block (0..127); lane: quad lane
+// within the wave.  FUSED: each wave sums gY.dY over its own columns; wave 1
+// leaves its partial sum in sacc[lane] for wave 0 (read after the final
+// barrier).
+template <typename T, int MM, bool NORM, bool FUSED, bool STORE, bool FAST, int LT>
+__device__ __forceinline__ void fwd4_tile_split(const Role<T>& ro, const Point<T>& pt, int64_t p0, int np,
+                                                int tid, int half, int lane, int lrow, const FwdParams& P,
+                                                T* st, T* sg, T* sacc, T& acc) {
+  constexpr int PT = kQuadWavePoints;
+  constexpr int NT = 2 * kWave;
+  constexpr int K = (LT + 1) * (LT + 1);
+  constexpr int S = K | 1;
+  constexpr int LS = split_degree<LT>();
+  constexpr int KS = LS * LS;  // first column of wave 1
+  const int p = lane >> 2;
+  if constexpr (FUSED) {
+    const T* src = static_cast<const T*>(P.gY) + p0 * K;
+    copy_in<NT>(sg, S, src, K, K, np, tid, aligned16(src));
+  }
+  T* row = st + lrow * S;
+  if (half == 0)
+    emit4_ct<T, LS - 1, NORM, 0, LS>(ro, pt, row);
+  else
+    emit4_ct<T, MM, NORM, LS, LT + 1>(ro, pt, row);
+  __syncthreads();
+  if constexpr (FUSED) {
+    const T* gr = sg + p * S;
+    T s0 = T(0), s1 = T(0);
+    if (half == 0) {
+#pragma unroll
+      for (int j = 0; j < KS; ++j) ((j & 1) ? s1 : s0) += gr[j] * row[j];
+      acc += s0 + s1;
+    } else {
+#pragma unroll
+      for (int j = KS; j < K; ++j) ((j & 1) ? s1 : s0) += gr[j] * row[j];
+      sacc[lane] = s0 + s1;
+    }
+  }
+  T* ydst = static_cast<T*>(P.Y) + p0 * K;
+  T* ddst = STORE ? static_cast<T*>(P.dY) + p0 * 3 * K : nullptr;
+  if constexpr (FAST) {
+    static_assert(S == K, "fast path needs one contiguous group");
+    constexpr int W = Vec16<T>::n;
+    copy_out_full<T, PT * K / W, NT>(st, ydst, tid);
+    if constexpr (STORE) copy_out_full<T, 3 * PT * K / W, NT>(st + PT * S, ddst, tid);
+  } else {
+    copy_out<NT>(st, S, ydst, K, K, np, tid, aligned16(ydst));
+    if constexpr (STORE) copy_out<NT>(st + PT * S, S, ddst, K, K, 3 * np, tid, aligned16(ddst));
+  }
+  __syncthreads();
+}
+
 // Whether a compile-time l_max has a single contiguous group (the fast
 // full-tile path).
 template <typename T, int LT>
@@ -323,7 +392,9 @@ constexpr bool quad_has_fast() {
 
 // LT >= 0: l_max = LT known at compile time (MM = LT, degree loops unrolled);
 // LT < 0: l_max = P.L <= MM at run time.  NW waves per block (a tile of
-// 16 NW points; quad_waves gives the default).  FUSED: the backward is fused
+// 16 NW points; quad_waves gives the default); DS = 2: the degrees of a
+// one-wave tile split between two waves (fwd4_tile_split).  FUSED: the
+// backward is fused
 // (P.gY, P.gxyz); STORE: dY is written.  Dynamic LDS: 4 PT rows of
 // stride(L) elements, plus PT rows for the upstream-gradient tile when FUSED.
 //
@@ -334,23 +405,27 @@ constexpr bool quad_has_fast() {
 // different numbers of memory operations would turn that wait into a drain
 // of every store of the tile, so the ragged last tile and unaligned outputs
 // take a separate general path.
-template <typename T, int MM, int LT, bool NORM, bool FUSED, bool STORE, int NW>
-__global__ __launch_bounds__(kWave * NW) void k_fwd4(FwdParams P) {
+template <typename T, int MM, int LT, bool NORM, bool FUSED, bool STORE, int NW, int DS>
+__global__ __launch_bounds__(kWave * NW * DS) void k_fwd4(FwdParams P) {
+  static_assert(DS == 1 || (DS == 2 && NW == 1 && LT >= 0), "degree split: one-wave tiles, compile-time l_max");
   constexpr int PT = kQuadWavePoints * NW;  // points per tile
-  constexpr int NT = kWave * NW;            // threads per block
+  constexpr int NQ = kWave * NW;            // quad lanes: four per point, also the tile's rows
   constexpr int B = kQuadBudget<T>;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int lane = threadIdx.x;  // 0 .. NT - 1
+  const int tid = threadIdx.x;  // 0 .. NQ * DS - 1
+  const int lane = DS == 1 ? tid : tid % NQ;
+  const int half = DS == 1 ? 0 : tid / NQ;
   const int L = LT >= 0 ? LT : P.L;
   const int K = (L + 1) * (L + 1);
   const int smax = plan_stride(L, B);
   T* st = reinterpret_cast<T*>(smem);
-  T* sg = st + NT * smax;
+  T* sg = st + NQ * smax;
+  T* sacc = sg + PT * smax;  // degree split, fused: wave 1's partial sums
   const int p = lane >> 2;
   const int r = lane & 3;
   const int lrow = (r == 0) ? p : PT + 3 * p + (r - 1);
 
-  if (P.status != nullptr && blockIdx.x == 0 && lane < kWave) check_offsets(P, lane);
+  if (P.status != nullptr && blockIdx.x == 0 && tid < kWave) check_offsets(P, tid);
 
   const T* xyz = static_cast<const T*>(P.xyz);
   auto tile_body = [&](int64_t tile, T x, T y, T z, auto fast_c) {
@@ -360,7 +435,11 @@ __global__ __launch_bounds__(kWave * NW) void k_fwd4(FwdParams P) {
     const Point<T> pt = make_point<T, NORM>(x, y, z);
     const Role<T> ro = make_role<T, NORM>(r, pt);
     T acc = T(0);
-    if constexpr (LT >= 0) {
+    if constexpr (DS == 2) {
+      static_assert(make_plan(LT, B).ng == 1, "degree split needs one group of degrees");
+      fwd4_tile_split<T, MM, NORM, FUSED, STORE, FAST, LT>(ro, pt, p0, np, tid, half, lane, lrow, P, st, sg, sacc,
+                                                           acc);
+    } else if constexpr (LT >= 0) {
       constexpr Plan PL = make_plan(LT, B);
       fwd4_groups_ct<T, NW, MM, NORM, FUSED, STORE, FAST, LT>(std::make_integer_sequence<int, PL.ng>{}, ro, pt, K,
                                                           p0, np, lane, lrow, P, st, sg, acc);
@@ -372,7 +451,8 @@ __global__ __launch_bounds__(kWave * NW) void k_fwd4(FwdParams P) {
       }
     }
     if constexpr (FUSED) {
-      if (r > 0 && p < np) static_cast<T*>(P.gxyz)[(p0 + p) * 3 + (r - 1)] = acc;
+      if constexpr (DS == 2) acc += sacc[lane];
+      if (half == 0 && r > 0 && p < np) static_cast<T*>(P.gxyz)[(p0 + p) * 3 + (r - 1)] = acc;
     }
   };
   auto load_point = [&](int64_t i, T& x, T& y, T& z) {

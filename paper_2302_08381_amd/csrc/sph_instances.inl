@@ -38,31 +38,43 @@ template <int LT>
 const void* alt_ptr() {
   return nullptr;
 }
+template <int LT>
+const void* split_ptr() {
+  return nullptr;
+}
 #else
 constexpr bool kFused = SPH_MODE != kDerivStore;
 constexpr bool kStore = SPH_MODE != kDerivFused;
 template <int MM, int LT>
 const void* kernel_ptr() {
-  return reinterpret_cast<const void*>(&k_fwd4<T, MM, LT, kNorm, kFused, kStore, quad_waves<T>(LT)>);
+  return reinterpret_cast<const void*>(&k_fwd4<T, MM, LT, kNorm, kFused, kStore, quad_waves<T>(LT), 1>);
 }
-// The compile-time kernel on a one-wave tile where the default takes two.
+// The compile-time kernel on an unsplit one-wave tile.
 template <int LT>
 const void* alt_ptr() {
-  if constexpr (quad_waves<T>(LT) == 2)
-    return reinterpret_cast<const void*>(&k_fwd4<T, LT, LT, kNorm, kFused, kStore, 1>);
+  return reinterpret_cast<const void*>(&k_fwd4<T, LT, LT, kNorm, kFused, kStore, 1, 1>);
+}
+// The compile-time one-wave tile with its degrees split between two waves
+// (l_max >= 4, where the default tile is one wave).
+template <int LT>
+const void* split_ptr() {
+  if constexpr (quad_waves<T>(LT) == 1 && LT >= 4)
+    return reinterpret_cast<const void*>(&k_fwd4<T, LT, LT, kNorm, kFused, kStore, 1, 2>);
   else
     return nullptr;
 }
 #endif
 
 template <int... Ls>
-void fill_spec(const void** out, const void** alt, std::integer_sequence<int, Ls...>) {
+void fill_spec(const void** out, const void** alt, const void** split, std::integer_sequence<int, Ls...>) {
   if constexpr (kSpecMax >= 0) {
     const void* v[] = {kernel_ptr<Ls, Ls>()...};
     const void* a[] = {alt_ptr<Ls>()...};
+    const void* d[] = {split_ptr<Ls>()...};
     for (size_t i = 0; i < sizeof...(Ls); ++i) {
       out[i] = v[i];
       alt[i] = a[i];
+      split[i] = d[i];
     }
   }
 }
@@ -76,9 +88,11 @@ void fill_buckets(const void** out, std::integer_sequence<int, Is...>) {
 struct Tables {
   const void* spec[kSpecSlots] = {};
   const void* spec_alt[kSpecSlots] = {};
+  const void* spec_split[kSpecSlots] = {};
   const void* buckets[kNumBuckets] = {};
   Tables() {
-    if constexpr (kSpecMax >= 0) fill_spec(spec, spec_alt, std::make_integer_sequence<int, kSpecSlots>{});
+    if constexpr (kSpecMax >= 0)
+      fill_spec(spec, spec_alt, spec_split, std::make_integer_sequence<int, kSpecSlots>{});
     fill_buckets(buckets, Buckets{});
   }
 };
@@ -108,18 +122,35 @@ const Tables& tables() {
 }
 
 #if SPH_FAMILY == 1 || SPH_FAMILY == 3
-// Kernel of a variant (see FwdVariant) and its tile width in waves.
-const void* pick(int L, int variant, int& nw, bool quad) {
+// Whether the degree-split tile is the default for a compile-time l_max.
+// Measured against the unsplit one-wave tile (Y+dY, N = 1e6): faster for
+// float l_max 9, 11, 12 (18-28 %) and double 5, 7, 8 (7-17 %), even for
+// double 6, 5 % slower for float 10.
+bool split_by_default(int L) {
+  return std::is_same_v<T, float> ? (L >= 9 && L != 10) : L >= 5;
+}
+
+// Kernel of a variant (see FwdVariant), its tile width in waves and its
+// degree-split factor (waves per tile width).
+const void* pick(int L, int variant, int& nw, int& ds, bool quad) {
   const bool ct = L <= kSpecMax;
   nw = 1;
+  ds = 1;
   switch (variant) {
     case kVarDefault:
+      if (ct && quad && tables().spec_split[L] != nullptr && split_by_default(L)) {
+        ds = 2;
+        return tables().spec_split[L];
+      }
       if (ct && quad) nw = quad_waves<T>(L);
       return ct ? tables().spec[L] : tables().buckets[bucket_index(L)];
     case kVarTile16:
       return ct ? tables().spec_alt[L] : nullptr;
     case kVarRuntime:
       return ct ? tables().buckets[bucket_index(L)] : nullptr;
+    case kVarSplit:
+      ds = 2;
+      return ct ? tables().spec_split[L] : nullptr;
     default:
       return nullptr;
   }
@@ -131,8 +162,8 @@ const void* pick(int L, int variant, int& nw, bool quad) {
 #if SPH_FAMILY == 1
 KernelInfo SPH_CAT(SPH_CAT(SPH_CAT(fwd_values_, SPH_SUFFIX), _n), SPH_NORM)(int L, int variant) {
   if (!in_range(L)) return KernelInfo{nullptr, 0, 0, 0, 0};
-  int nw = 1;
-  const void* fn = pick(L, variant, nw, false);
+  int nw = 1, ds = 1;
+  const void* fn = pick(L, variant, nw, ds, false);
   if (fn == nullptr) return KernelInfo{nullptr, 0, 0, 0, 0};
   const size_t lds = sizeof(T) * kWave * static_cast<size_t>(plan_stride(L, kValueBudget<T>));
   return KernelInfo{fn, lds, lds, kWave, kWave};
@@ -141,12 +172,14 @@ KernelInfo SPH_CAT(SPH_CAT(SPH_CAT(fwd_values_, SPH_SUFFIX), _n), SPH_NORM)(int 
 KernelInfo SPH_CAT(SPH_CAT(SPH_CAT(SPH_CAT(SPH_CAT(fwd_derivs_, SPH_SUFFIX), _n), SPH_NORM), _m), SPH_MODE)(
     int L, int variant) {
   if (!in_range(L)) return KernelInfo{nullptr, 0, 0, 0, 0};
-  int nw = 1;
-  const void* fn = pick(L, variant, nw, true);
+  int nw = 1, ds = 1;
+  const void* fn = pick(L, variant, nw, ds, true);
   if (fn == nullptr) return KernelInfo{nullptr, 0, 0, 0, 0};
   const size_t row = sizeof(T) * static_cast<size_t>(plan_stride(L, kQuadBudget<T>));
-  const int pts = kQuadWavePoints * nw, thr = kWave * nw;
-  return KernelInfo{fn, row * static_cast<size_t>(4 * pts), row * static_cast<size_t>(5 * pts), pts, thr};
+  const int pts = kQuadWavePoints * nw, thr = kWave * nw * ds;
+  // fused: the upstream-gradient tile, and the split kernel's partial sums
+  const size_t fused = row * static_cast<size_t>(5 * pts) + (ds == 2 ? sizeof(T) * kWave : 0);
+  return KernelInfo{fn, row * static_cast<size_t>(4 * pts), fused, pts, thr};
 }
 #else
 KernelInfo SPH_CAT(bwd_info_, SPH_SUFFIX)(int L) {

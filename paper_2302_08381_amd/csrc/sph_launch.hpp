@@ -62,15 +62,18 @@ struct KernelInfo {
 //   derivatives: four lanes per point, 32- or 16-point tiles; mode
 //                kDerivStore (Y and dY), kDerivFusedStore (Y, dY and the
 //                fused backward), kDerivFused (Y and the fused backward)
-// Variants (the batched autotuner's candidates):
-//   kVarDefault  the compile-time (unrolled) kernel where one exists, with its
-//                default tile, else the run-time-degree kernel
-//   kVarTile16   the compile-time kernel on a 16-point, one-wave tile where
-//                the default tile is 32 points (float, l_max <= 8)
+// Variants (the batched autotuner's candidates; two may name one kernel):
+//   kVarDefault  the compile-time (unrolled) kernel where one exists, on its
+//                default tile (32 points on two waves for float l_max <= 8,
+//                the degree-split tile where that measured faster, else 16
+//                points on one wave), else the run-time-degree kernel
+//   kVarTile16   the compile-time kernel on an unsplit 16-point, one-wave tile
 //   kVarRuntime  the run-time-degree (not unrolled) kernel where the default
 //                is a compile-time one
+//   kVarSplit    the compile-time kernel on a 16-point tile whose degrees are
+//                split between two waves (float l_max 9..12, double 4..8)
 enum DerivMode { kDerivStore = 0, kDerivFusedStore = 1, kDerivFused = 2, kNumDerivModes = 3 };
-enum FwdVariant { kVarDefault = 0, kVarTile16 = 1, kVarRuntime = 2, kNumFwdVariants = 3 };
+enum FwdVariant { kVarDefault = 0, kVarTile16 = 1, kVarRuntime = 2, kVarSplit = 3, kNumFwdVariants = 4 };
 KernelInfo fwd_values_f32_n0(int L, int variant);
 KernelInfo fwd_values_f32_n1(int L, int variant);
 KernelInfo fwd_values_f64_n0(int L, int variant);

@@ -114,9 +114,11 @@ def test_set_config_validation(lib):
     assert c(8, 2, 0, 1, 1, 0, 0) == 2         # normalize
     assert c(8, 1, 7, 1, 1, 0, 0) == 2         # dtype
     assert c(8, 1, 0, 2, 1, 0, 0) == 2         # store_dY flag
-    assert c(8, 1, 0, 1, 1, 3, 0) == 2         # unknown variant
+    assert c(8, 1, 0, 1, 1, 4, 0) == 2         # unknown variant
+    assert c(8, 1, 0, 1, 1, 3, 0) == 2         # degree_split does not exist for float l_max = 8
+    assert c(3, 1, 1, 1, 1, 3, 0) == 2         # ... nor for double l_max = 3
     assert c(8, 1, 0, 1, 1, 0, 65) == 2        # blocks_per_cu
-    assert c(8, 1, 1, 1, 1, 1, 0) == 2         # tile16 does not exist for float64
-    assert c(12, 1, 0, 1, 1, 1, 0) == 2        # ... nor for float l_max = 12
+    assert c(13, 1, 0, 1, 1, 1, 0) == 2        # tile16 does not exist past the unrolled kernels
+    assert c(9, 1, 1, 1, 1, 1, 0) == 2         # ... (double: l_max <= 8)
     assert c(8, 1, 0, 0, 0, 1, 0) == 2         # ... nor for the values-only kernel
     assert c(20, 1, 0, 1, 1, 2, 0) == 2        # runtime_degree is already the default at l_max = 20

@@ -172,13 +172,13 @@ def test_every_batched_variant_matches_oracle(l_max):
     _, gsc, _ = oracle.component_scales(hp, l_max, True)
     gscale = (np.abs(gYh) * gsc).sum(1)[:, None]
     ran = []
-    for variant in ("default", "tile16", "runtime_degree"):
+    for variant in ("default", "tile16", "runtime_degree", "degree_split"):
         for bpc in (0, 4):
             print(f"batched variant l_max={l_max} {variant} bpc={bpc}", flush=True)
             try:
                 sph.sph_batched_set_config(l_max, True, torch.float32, True, True, variant, bpc)
             except sph.SphError:
-                assert variant == "tile16" and l_max > 8
+                assert variant == "degree_split" and l_max <= 8
                 continue
             cfg = sph.sph_batched_get_config(l_max, True, torch.float32, True, True)
             assert f"kernel={variant}" in cfg and f"blocks_per_cu={bpc}" in cfg
@@ -190,4 +190,5 @@ def test_every_batched_variant_matches_oracle(l_max):
             assert err.max() <= TOL[torch.float32], (variant, bpc, err.max())
             ran.append(variant)
     assert "default" in ran and "runtime_degree" in ran
+    assert ("degree_split" in ran) == (l_max > 8)
     sph.sph_batched_set_config(l_max, True, torch.float32, True, True, "default", 0)
