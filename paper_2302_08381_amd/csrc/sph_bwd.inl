@@ -41,7 +41,7 @@ __global__ __launch_bounds__(kWave * NW) void k_bwd(BwdParams P) {
   constexpr int PP = 16 * NW;   // points per block
   constexpr int NT = kWave * NW;
   constexpr int KC = bwd_chunk<T, NW>();
-  constexpr int SC = KC | 1;
+  constexpr int SC = KC + Vec16<T>::n;  // >= row_stride of any chunk
   __shared__ __align__(16) T sg[PP * SC];
   __shared__ __align__(16) T sd[3 * PP * SC];
   const int K = P.K;
@@ -60,7 +60,7 @@ __global__ __launch_bounds__(kWave * NW) void k_bwd(BwdParams P) {
   T a0 = T(0), a1 = T(0), a2 = T(0);
   for (int kc0 = 0; kc0 < K; kc0 += ch) {
     const int cnt = (K - kc0) < ch ? (K - kc0) : ch;
-    const int S = cnt | 1;
+    const int S = row_stride<T>(cnt, cnt == K);
     if (cnt == K && S == K && aligned16(gY) && aligned16(dY)) {
       // one chunk of whole rows: the gY and dY blocks share the round trips
       copy_in_pair<NT, kBwdPairBatch<T>>(sg, gY, np * K, sd, dY, 3 * np * K, lane);

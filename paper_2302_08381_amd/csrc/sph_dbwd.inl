@@ -240,7 +240,7 @@ __global__ __launch_bounds__(kWave) void k_dbwd(DbwdParams P) {
     const int lb = group_end(la, L, B);
     const int kb = la * la;
     const int cnt = lb * lb - kb;
-    const int S = cnt | 1;
+    const int S = row_stride<T>(cnt, cnt == K);
     const T* src = static_cast<const T*>(P.gY) + p0 * K + kb;
     copy_in(st, S, src, K, cnt, np, lane, aligned16(src));
     __syncthreads();

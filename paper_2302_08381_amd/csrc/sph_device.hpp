@@ -125,6 +125,28 @@ __host__ __device__ constexpr int group_end(int la, int L, int budget) {
   return lb;
 }
 
+// LDS row stride (elements) of a group of cnt columns.  An odd cnt is its
+// own stride: the rows stay contiguous and one column written by a wave hits
+// distinct banks.  An even group that spans whole rows (one group of degrees)
+// keeps rows that start on 16-byte boundaries, so the tile can still leave
+// with 16-byte stores: cnt itself when cnt / W is odd (contiguous rows), else
+// cnt + W.  Partial-row groups of even cnt: cnt + 1.
+template <typename T>
+__host__ __device__ constexpr int row_stride(int cnt, bool whole_rows) {
+  constexpr int W = 16 / static_cast<int>(sizeof(T));
+  if (cnt % 2 == 1) return cnt;
+  if (!whole_rows || cnt % W != 0) return cnt + 1;
+  return ((cnt / W) % 2 == 1) ? cnt : cnt + W;
+}
+
+// LDS stride per point of the plan for l_max = L: row_stride of the whole
+// row for a one-group plan, the odd plan stride otherwise.
+template <typename T>
+__host__ __device__ constexpr int tile_stride(int L, int budget) {
+  if (group_end(0, L, budget) > L) return row_stride<T>((L + 1) * (L + 1), true);
+  return plan_stride(L, budget);
+}
+
 // m-extent buckets: a kernel instantiated for MM serves every l_max <= MM
 // (its m loops are unrolled to MM and exit at the row's degree).
 constexpr int kNumBuckets = 8;
@@ -313,9 +335,37 @@ template <int NT = kWave, int NB = kBatch, typename T>
 __device__ __forceinline__ void copy_out(const T* __restrict__ st, int S, T* __restrict__ dst,
                                          int gstride, int cnt, int rows, int lane, bool vec) {
   const int total = rows * cnt;
+  constexpr int W = Vec16<T>::n;
+  if (vec && gstride == cnt && S != cnt && cnt % W == 0 && S % W == 0) {
+    // whole rows, 16-byte aligned LDS rows with padding: vector i of the
+    // block is vector (i / CV, i % CV) of the tile, walked incrementally
+    using V = typename Vec16<T>::type;
+    const int CV = cnt / W, SV = S / W;
+    const int nv = rows * CV;
+    const V* sv = reinterpret_cast<const V*>(st);
+    const __amdgpu_buffer_rsrc_t rs = stream_rsrc(dst, nv * 16);
+    int r = lane / CV, c = lane - r * CV;
+    const int qs = NT / CV, rq = NT - qs * CV;
+    for (int i0 = lane; i0 < nv; i0 += NT * NB) {
+      V v[NB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        if (i0 + u * NT < nv) v[u] = sv[r * SV + c];
+        r += qs;
+        c += rq;
+        if (c >= CV) {
+          c -= CV;
+          ++r;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < NB; ++u)
+        if (i0 + u * NT < nv) stream_store16(v[u], rs, (i0 + u * NT) * 16);
+    }
+    return;
+  }
   if (vec && gstride == cnt && S == cnt) {
     using V = typename Vec16<T>::type;
-    constexpr int W = Vec16<T>::n;
     const int nv = total / W;
     const V* sv = reinterpret_cast<const V*>(st);
     const __amdgpu_buffer_rsrc_t rs = stream_rsrc(dst, nv * 16);
@@ -359,9 +409,38 @@ template <int NT = kWave, int NB = kBatch, typename T>
 __device__ __forceinline__ void copy_in(T* __restrict__ st, int S, const T* __restrict__ src,
                                         int gstride, int cnt, int rows, int lane, bool vec) {
   const int total = rows * cnt;
+  constexpr int W = Vec16<T>::n;
+  if (vec && gstride == cnt && S != cnt && cnt % W == 0 && S % W == 0) {
+    // whole rows into padded, 16-byte aligned LDS rows (as in copy_out)
+    using V = typename Vec16<T>::type;
+    const int CV = cnt / W, SV = S / W;
+    const int nv = rows * CV;
+    V* sv = reinterpret_cast<V*>(st);
+    const V* dv = reinterpret_cast<const V*>(src);
+    int r = lane / CV, c = lane - r * CV;
+    const int qs = NT / CV, rq = NT - qs * CV;
+    for (int i0 = lane; i0 < nv; i0 += NT * NB) {
+      V v[NB];
+      int o[NB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        o[u] = r * SV + c;
+        if (i0 + u * NT < nv) v[u] = __builtin_nontemporal_load(dv + i0 + u * NT);
+        r += qs;
+        c += rq;
+        if (c >= CV) {
+          c -= CV;
+          ++r;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < NB; ++u)
+        if (i0 + u * NT < nv) sv[o[u]] = v[u];
+    }
+    return;
+  }
   if (vec && gstride == cnt && S == cnt) {
     using V = typename Vec16<T>::type;
-    constexpr int W = Vec16<T>::n;
     const int nv = total / W;
     V* sv = reinterpret_cast<V*>(st);
     const V* dv = reinterpret_cast<const V*>(src);
@@ -438,19 +517,22 @@ __device__ __forceinline__ void copy_in_pair(T* __restrict__ sa, const T* __rest
 // except on the last, partial sweep.
 constexpr int kBatchFull = 8;
 
-template <typename T, int NV, int NT = kWave>
+// CV, SV: 16-byte vectors per row in global memory and in LDS (SV > CV for
+// padded LDS rows; vector i of the block is LDS vector (i / CV) SV + i % CV).
+template <typename T, int NV, int NT = kWave, int CV = 1, int SV = 1>
 __device__ __forceinline__ void copy_out_full(const T* __restrict__ st, T* __restrict__ dst, int lane) {
   using V = typename Vec16<T>::type;
   const V* sv = reinterpret_cast<const V*>(st);
   const __amdgpu_buffer_rsrc_t rs = stream_rsrc(dst, NV * 16);
   constexpr int kSweeps = (NV + NT - 1) / NT;
+  auto at = [](int i) { return CV == SV ? i : (i / CV) * SV + i % CV; };
 #pragma unroll
   for (int s0 = 0; s0 < kSweeps; s0 += kBatchFull) {
     V v[kBatchFull];
 #pragma unroll
     for (int u = 0; u < kBatchFull; ++u) {
       const int sw = s0 + u;
-      if (sw < kSweeps && (sw < NV / NT || lane + sw * NT < NV)) v[u] = sv[lane + sw * NT];
+      if (sw < kSweeps && (sw < NV / NT || lane + sw * NT < NV)) v[u] = sv[at(lane + sw * NT)];
     }
 #pragma unroll
     for (int u = 0; u < kBatchFull; ++u) {

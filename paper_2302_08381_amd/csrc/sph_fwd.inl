@@ -40,12 +40,12 @@ __device__ __forceinline__ void emit_values(const Point<T>& pt, int la, int lb, 
   }
 }
 
-template <typename T, int MM, bool NORM, bool FAST, int LA, int LB>
+template <typename T, int MM, bool NORM, bool FAST, bool WHOLE, int LA, int LB>
 __device__ __forceinline__ void values_group_ct(const Point<T>& pt, int K, int64_t p0, int np, int lane,
                                                 const FwdParams& P, T* st) {
   constexpr int kb = LA * LA;
   constexpr int cnt = LB * LB - kb;
-  constexpr int S = cnt | 1;
+  constexpr int S = row_stride<T>(cnt, WHOLE);
   T* row = st + lane * S - kb;
   T cur[MM + 3], unused[MM + 3];
 #pragma unroll
@@ -56,8 +56,10 @@ __device__ __forceinline__ void values_group_ct(const Point<T>& pt, int K, int64
   __syncthreads();
   T* dst = static_cast<T*>(P.Y) + p0 * K + kb;
   if constexpr (FAST) {
-    static_assert(S == cnt && kb == 0, "fast path needs one contiguous group");
-    copy_out_full<T, kWave * cnt / Vec16<T>::n>(st, dst, lane);
+    static_assert(WHOLE && kb == 0, "fast path needs one group of whole rows");
+    constexpr int W = Vec16<T>::n;
+    constexpr int CV = S == cnt ? 1 : cnt / W, SV = S == cnt ? 1 : S / W;
+    copy_out_full<T, kWave * cnt / W, kWave, CV, SV>(st, dst, lane);
   } else {
     copy_out(st, S, dst, K, cnt, np, lane, aligned16(dst));
   }
@@ -68,7 +70,7 @@ template <typename T, int MM, bool NORM, bool FAST, int LT, int... Gs>
 __device__ __forceinline__ void values_groups_ct(std::integer_sequence<int, Gs...>, const Point<T>& pt, int K,
                                                  int64_t p0, int np, int lane, const FwdParams& P, T* st) {
   constexpr Plan PL = make_plan(LT, kValueBudget<T>);
-  (values_group_ct<T, MM, NORM, FAST, PL.lo[Gs], PL.hi[Gs]>(pt, K, p0, np, lane, P, st), ...);
+  (values_group_ct<T, MM, NORM, FAST, PL.ng == 1, PL.lo[Gs], PL.hi[Gs]>(pt, K, p0, np, lane, P, st), ...);
 }
 
 template <typename T, int LT>
@@ -78,7 +80,7 @@ constexpr bool values_has_fast() {
   } else {
     constexpr Plan PL = make_plan(LT, kValueBudget<T>);
     constexpr int K = (LT + 1) * (LT + 1);
-    return PL.ng == 1 && (K % 2 == 1);
+    return PL.ng == 1 && (K % 2 == 1 || K % Vec16<T>::n == 0);
   }
 }
 
@@ -112,7 +114,7 @@ __global__ __launch_bounds__(kWave) void k_fwd(FwdParams P) {
         const int lb = group_end(la, L, B);
         const int kb = la * la;
         const int cnt = lb * lb - kb;
-        const int S = cnt | 1;
+        const int S = row_stride<T>(cnt, cnt == K);
         emit_values<T, MM, NORM, false>(pt, la, lb, st + lane * S - kb);
         __syncthreads();
         T* dst = static_cast<T*>(P.Y) + p0 * K + kb;

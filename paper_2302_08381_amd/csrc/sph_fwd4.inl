@@ -219,7 +219,7 @@ __device__ __forceinline__ void fwd4_group(const Role<T>& ro, const Point<T>& pt
   constexpr int NT = kWave * NW;
   const int kb = la * la;
   const int cnt = lb * lb - kb;
-  const int S = cnt | 1;
+  const int S = row_stride<T>(cnt, cnt == K);
   constexpr bool bwd = FUSED;
   const int p = lane >> 2;
   if (bwd) {
@@ -255,14 +255,14 @@ __device__ __forceinline__ void fwd4_group(const Role<T>& ro, const Point<T>& pt
 // One compile-time group of degrees [LA, LB).  FAST: a full tile of
 // a one-group plan with 16-byte aligned outputs, copied out with the
 // fixed-size unpredicated copy; otherwise the general copy.
-template <typename T, int NW, int MM, bool NORM, bool FUSED, bool STORE, bool FAST, int LA, int LB>
+template <typename T, int NW, int MM, bool NORM, bool FUSED, bool STORE, bool FAST, bool WHOLE, int LA, int LB>
 __device__ __forceinline__ void fwd4_group_ct(const Role<T>& ro, const Point<T>& pt, int K, int64_t p0, int np,
                                               int lane, int lrow, const FwdParams& P, T* st, T* sg, T& acc) {
   constexpr int PT = kQuadWavePoints * NW;
   constexpr int NT = kWave * NW;
   constexpr int kb = LA * LA;
   constexpr int cnt = LB * LB - kb;
-  constexpr int S = cnt | 1;
+  constexpr int S = row_stride<T>(cnt, WHOLE);
   const int p = lane >> 2;
   if constexpr (FUSED) {
     const T* src = static_cast<const T*>(P.gY) + p0 * K + kb;
@@ -285,11 +285,12 @@ __device__ __forceinline__ void fwd4_group_ct(const Role<T>& ro, const Point<T>&
   T* ydst = static_cast<T*>(P.Y) + p0 * K + kb;
   T* ddst = STORE ? static_cast<T*>(P.dY) + p0 * 3 * K + kb : nullptr;
   if constexpr (FAST) {
-    static_assert(S == cnt && kb == 0, "fast path needs one contiguous group");
+    static_assert(WHOLE && kb == 0, "fast path needs one group of whole rows");
     constexpr int W = Vec16<T>::n;
-    copy_out_full<T, PT * cnt / W, NT>(st, ydst, lane);
+    constexpr int CV = S == cnt ? 1 : cnt / W, SV = S == cnt ? 1 : S / W;
+    copy_out_full<T, PT * cnt / W, NT, CV, SV>(st, ydst, lane);
     if constexpr (STORE)
-      copy_out_full<T, 3 * PT * cnt / W, NT>(st + PT * S, ddst, lane);
+      copy_out_full<T, 3 * PT * cnt / W, NT, CV, SV>(st + PT * S, ddst, lane);
   } else {
     copy_out<NT>(st, S, ydst, K, cnt, np, lane, aligned16(ydst));
     if constexpr (STORE)
@@ -303,8 +304,8 @@ __device__ __forceinline__ void fwd4_groups_ct(std::integer_sequence<int, Gs...>
                                                const Point<T>& pt, int K, int64_t p0, int np, int lane,
                                                int lrow, const FwdParams& P, T* st, T* sg, T& acc) {
   constexpr Plan PL = make_plan(LT, kQuadBudget<T>);
-  (fwd4_group_ct<T, NW, MM, NORM, FUSED, STORE, FAST, PL.lo[Gs], PL.hi[Gs]>(ro, pt, K, p0, np, lane, lrow, P, st,
-                                                                            sg, acc),
+  (fwd4_group_ct<T, NW, MM, NORM, FUSED, STORE, FAST, PL.ng == 1, PL.lo[Gs], PL.hi[Gs]>(ro, pt, K, p0, np, lane,
+                                                                                       lrow, P, st, sg, acc),
    ...);
 }
 
@@ -336,7 +337,7 @@ __device__ __forceinline__ void fwd4_tile_split(const Role<T>& ro, const Point<T
   constexpr int PT = kQuadWavePoints;
   constexpr int NT = 2 * kWave;
   constexpr int K = (LT + 1) * (LT + 1);
-  constexpr int S = K | 1;
+  constexpr int S = row_stride<T>(K, true);
   constexpr int LS = split_degree<LT>();
   constexpr int KS = LS * LS;  // first column of wave 1
   const int p = lane >> 2;
@@ -366,10 +367,10 @@ __device__ __forceinline__ void fwd4_tile_split(const Role<T>& ro, const Point<T
   T* ydst = static_cast<T*>(P.Y) + p0 * K;
   T* ddst = STORE ? static_cast<T*>(P.dY) + p0 * 3 * K : nullptr;
   if constexpr (FAST) {
-    static_assert(S == K, "fast path needs one contiguous group");
     constexpr int W = Vec16<T>::n;
-    copy_out_full<T, PT * K / W, NT>(st, ydst, tid);
-    if constexpr (STORE) copy_out_full<T, 3 * PT * K / W, NT>(st + PT * S, ddst, tid);
+    constexpr int CV = S == K ? 1 : K / W, SV = S == K ? 1 : S / W;
+    copy_out_full<T, PT * K / W, NT, CV, SV>(st, ydst, tid);
+    if constexpr (STORE) copy_out_full<T, 3 * PT * K / W, NT, CV, SV>(st + PT * S, ddst, tid);
   } else {
     copy_out<NT>(st, S, ydst, K, K, np, tid, aligned16(ydst));
     if constexpr (STORE) copy_out<NT>(st + PT * S, S, ddst, K, K, 3 * np, tid, aligned16(ddst));
@@ -386,7 +387,7 @@ constexpr bool quad_has_fast() {
   } else {
     constexpr Plan PL = make_plan(LT, kQuadBudget<T>);
     constexpr int K = (LT + 1) * (LT + 1);
-    return PL.ng == 1 && (K % 2 == 1);
+    return PL.ng == 1 && (K % 2 == 1 || K % Vec16<T>::n == 0);
   }
 }
 
@@ -417,7 +418,7 @@ __global__ __launch_bounds__(kWave * NW * DS) void k_fwd4(FwdParams P) {
   const int half = DS == 1 ? 0 : tid / NQ;
   const int L = LT >= 0 ? LT : P.L;
   const int K = (L + 1) * (L + 1);
-  const int smax = plan_stride(L, B);
+  const int smax = tile_stride<T>(L, B);
   T* st = reinterpret_cast<T*>(smem);
   T* sg = st + NQ * smax;
   T* sacc = sg + PT * smax;  // degree split, fused: wave 1's partial sums

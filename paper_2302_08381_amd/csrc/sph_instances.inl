@@ -165,7 +165,7 @@ KernelInfo SPH_CAT(SPH_CAT(SPH_CAT(fwd_values_, SPH_SUFFIX), _n), SPH_NORM)(int 
   int nw = 1, ds = 1;
   const void* fn = pick(L, variant, nw, ds, false);
   if (fn == nullptr) return KernelInfo{nullptr, 0, 0, 0, 0};
-  const size_t lds = sizeof(T) * kWave * static_cast<size_t>(plan_stride(L, kValueBudget<T>));
+  const size_t lds = sizeof(T) * kWave * static_cast<size_t>(tile_stride<T>(L, kValueBudget<T>));
   return KernelInfo{fn, lds, lds, kWave, kWave};
 }
 #elif SPH_FAMILY == 3
@@ -175,7 +175,7 @@ KernelInfo SPH_CAT(SPH_CAT(SPH_CAT(SPH_CAT(SPH_CAT(fwd_derivs_, SPH_SUFFIX), _n)
   int nw = 1, ds = 1;
   const void* fn = pick(L, variant, nw, ds, true);
   if (fn == nullptr) return KernelInfo{nullptr, 0, 0, 0, 0};
-  const size_t row = sizeof(T) * static_cast<size_t>(plan_stride(L, kQuadBudget<T>));
+  const size_t row = sizeof(T) * static_cast<size_t>(tile_stride<T>(L, kQuadBudget<T>));
   const int pts = kQuadWavePoints * nw, thr = kWave * nw * ds;
   // fused: the upstream-gradient tile, and the split kernel's partial sums
   const size_t fused = row * static_cast<size_t>(5 * pts) + (ds == 2 ? sizeof(T) * kWave : 0);
@@ -190,7 +190,7 @@ KernelInfo SPH_CAT(bwd_info_, SPH_SUFFIX)(int L) {
 
 KernelInfo SPH_CAT(dbwd_info_, SPH_SUFFIX)(int L, int normalize) {
   if (!in_range(L) || (normalize != 0 && normalize != 1)) return KernelInfo{nullptr, 0, 0, 0, 0};
-  const size_t lds = sizeof(T) * kWave * static_cast<size_t>(plan_stride(L, kDbwdBudget<T>));
+  const size_t lds = sizeof(T) * kWave * static_cast<size_t>(tile_stride<T>(L, kDbwdBudget<T>));
   return KernelInfo{tables().dbwd[normalize][bucket_index(L)], lds, lds, kWave, kWave};
 }
 #endif

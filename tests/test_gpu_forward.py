@@ -12,7 +12,7 @@ from _gpu_common import TOL, assert_close_per_l, host_points, to_dev
 
 pytestmark = pytest.mark.gpu
 
-LMAXES = [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 13, 16, 17, 20, 24, 25, 32]
+LMAXES = [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 16, 17, 20, 24, 25, 32]
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
