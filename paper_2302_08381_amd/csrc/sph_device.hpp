@@ -512,6 +512,31 @@ __device__ __forceinline__ void copy_in_pair(T* __restrict__ sa, const T* __rest
   for (int j = nvb * W + lane; j < nb; j += NT) sb[j] = __builtin_nontemporal_load(b + j);
 }
 
+// A full tile of whole rows, loaded in two halves so that the memory latency
+// overlaps other work: prefetch() issues the 16-byte loads of NV vectors of
+// src into registers (NT threads, thread lane), commit() writes them to LDS
+// rows of SV vectors (CV per row: the same row geometry as copy_out_full).
+template <typename T, int NV, int NT, int CV = 1, int SV = 1>
+struct TilePrefetch {
+  using V = typename Vec16<T>::type;
+  static constexpr int kPer = (NV + NT - 1) / NT;
+  V v[kPer];
+  __device__ __forceinline__ void prefetch(const T* __restrict__ src, int lane) {
+    const V* g = reinterpret_cast<const V*>(src);
+#pragma unroll
+    for (int u = 0; u < kPer; ++u)
+      if (u < NV / NT || lane + u * NT < NV) v[u] = __builtin_nontemporal_load(g + lane + u * NT);
+  }
+  __device__ __forceinline__ void commit(T* __restrict__ st, int lane) const {
+    V* d = reinterpret_cast<V*>(st);
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int i = lane + u * NT;
+      if (u < NV / NT || i < NV) d[CV == SV ? i : (i / CV) * SV + i % CV] = v[u];
+    }
+  }
+};
+
 // Full-tile contiguous copy with compile-time size: NV 16-byte vectors from
 // LDS to global by NT threads, kBatchFull in flight per lane, no predication
 // except on the last, partial sweep.

@@ -263,12 +263,21 @@ __device__ __forceinline__ void fwd4_group_ct(const Role<T>& ro, const Point<T>&
   constexpr int kb = LA * LA;
   constexpr int cnt = LB * LB - kb;
   constexpr int S = row_stride<T>(cnt, WHOLE);
+  constexpr int W = Vec16<T>::n;
   const int p = lane >> 2;
-  if constexpr (FUSED) {
+  // full tiles: the upstream-gradient tile is loaded into registers before
+  // the emission and written to LDS after it, so its latency is hidden
+  constexpr bool kPre = FUSED && FAST;
+  constexpr int GCV = S == cnt ? 1 : cnt / W, GSV = S == cnt ? 1 : S / W;
+  TilePrefetch<T, kPre ? PT * cnt / W : 1, NT, GCV, GSV> gpre;
+  if constexpr (kPre) {
+    gpre.prefetch(static_cast<const T*>(P.gY) + p0 * K, lane);
+  } else if constexpr (FUSED) {
     const T* src = static_cast<const T*>(P.gY) + p0 * K + kb;
     copy_in<NT>(sg, S, src, K, cnt, np, lane, aligned16(src));
   }
   emit4_ct<T, MM, NORM, LA, LB>(ro, pt, st + lrow * S - kb);
+  if constexpr (kPre) gpre.commit(sg, lane);
   __syncthreads();
   if constexpr (FUSED) {
     const T* gr = sg + p * S;
@@ -286,7 +295,6 @@ __device__ __forceinline__ void fwd4_group_ct(const Role<T>& ro, const Point<T>&
   T* ddst = STORE ? static_cast<T*>(P.dY) + p0 * 3 * K + kb : nullptr;
   if constexpr (FAST) {
     static_assert(WHOLE && kb == 0, "fast path needs one group of whole rows");
-    constexpr int W = Vec16<T>::n;
     constexpr int CV = S == cnt ? 1 : cnt / W, SV = S == cnt ? 1 : S / W;
     copy_out_full<T, PT * cnt / W, NT, CV, SV>(st, ydst, lane);
     if constexpr (STORE)
@@ -341,7 +349,13 @@ __device__ __forceinline__ void fwd4_tile_split(const Role<T>& ro, const Point<T
   constexpr int LS = split_degree<LT>();
   constexpr int KS = LS * LS;  // first column of wave 1
   const int p = lane >> 2;
-  if constexpr (FUSED) {
+  constexpr int W = Vec16<T>::n;
+  constexpr bool kPre = FUSED && FAST;  // as in fwd4_group_ct
+  constexpr int GCV = S == K ? 1 : K / W, GSV = S == K ? 1 : S / W;
+  TilePrefetch<T, kPre ? PT * K / W : 1, NT, GCV, GSV> gpre;
+  if constexpr (kPre) {
+    gpre.prefetch(static_cast<const T*>(P.gY) + p0 * K, tid);
+  } else if constexpr (FUSED) {
     const T* src = static_cast<const T*>(P.gY) + p0 * K;
     copy_in<NT>(sg, S, src, K, K, np, tid, aligned16(src));
   }
@@ -350,6 +364,7 @@ __device__ __forceinline__ void fwd4_tile_split(const Role<T>& ro, const Point<T
     emit4_ct<T, LS - 1, NORM, 0, LS>(ro, pt, row);
   else
     emit4_ct<T, MM, NORM, LS, LT + 1>(ro, pt, row);
+  if constexpr (kPre) gpre.commit(sg, tid);
   __syncthreads();
   if constexpr (FUSED) {
     const T* gr = sg + p * S;
@@ -367,7 +382,6 @@ __device__ __forceinline__ void fwd4_tile_split(const Role<T>& ro, const Point<T
   T* ydst = static_cast<T*>(P.Y) + p0 * K;
   T* ddst = STORE ? static_cast<T*>(P.dY) + p0 * 3 * K : nullptr;
   if constexpr (FAST) {
-    constexpr int W = Vec16<T>::n;
     constexpr int CV = S == K ? 1 : K / W, SV = S == K ? 1 : S / W;
     copy_out_full<T, PT * K / W, NT, CV, SV>(st, ydst, tid);
     if constexpr (STORE) copy_out_full<T, 3 * PT * K / W, NT, CV, SV>(st + PT * S, ddst, tid);
@@ -464,7 +478,7 @@ __global__ __launch_bounds__(kWave * NW * DS) void k_fwd4(FwdParams P) {
   };
 
   constexpr bool kFast = quad_has_fast<T, LT>();
-  const bool aligned = aligned16(P.Y) && (!STORE || aligned16(P.dY));
+  const bool aligned = aligned16(P.Y) && (!STORE || aligned16(P.dY)) && (!FUSED || aligned16(P.gY));
   const int64_t slot = xcd_slot(blockIdx.x, gridDim.x);  // first tile of this block
   if (kFast && aligned) {
     const int64_t nfull = P.n / PT;
