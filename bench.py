@@ -9,8 +9,9 @@ normalised harmonics.  Inputs are resident in HBM before timing starts.
 Prints ONE JSON line:  points/s (value), ms per step, the roofline of the
 dominant kernel (algorithmic bytes per launch / mean launch time from HIP
 events recorded around each launch on the launch stream), the per-kernel
-figures, the accuracy of sampled rows against the float64 oracle, and the
-oracle itself timed on the host cores (a bounded sample).
+figures, secondary measurements of the other workloads, and the oracle timed
+on the host cores on a bounded sample; the oracle's results for 2048 rows of
+that sample also check the GPU's rows (accuracy).
 
     python bench.py [--gpus 1] [--steps 50] [--warmup 10] [--no-cpu-baseline]
 
@@ -159,9 +160,12 @@ def summarize(outdir: str) -> None:
     print("\n".join(lines + [""] + md))
 
 
-def cpu_baseline(n_sample: int = 200_000, chunk: int = 20_000):
+def cpu_baseline(gpu_rows, n_sample: int = 200_000, chunk: int = 20_000, rows: int = 2048):
     """The oracle (longdouble, single thread) on the first n_sample points of
-    the same workload: forward with gradients plus the backward contraction."""
+    the same workload: forward with gradients plus the backward contraction,
+    timed.  The oracle's results for `rows` random rows of the first chunk
+    also check the GPU's outputs for those rows: gpu_rows(idx) returns the
+    GPU's (Y, dY, grad_xyz) rows idx as host arrays."""
     import numpy as np
 
     import oracle
@@ -170,34 +174,30 @@ def cpu_baseline(n_sample: int = 200_000, chunk: int = 20_000):
     pts = standard_normal_points(N_POINTS, SEEDS["plain_gpu"])[:n_sample].astype(np.float32)
     K = (L_MAX + 1) ** 2
     gY = standard_normal((N_POINTS, K), SEEDS["plain_gpu_grad"])[:n_sample].astype(np.float32)
+    idx = np.sort(np.random.default_rng(7).choice(min(chunk, n_sample), rows, replace=False))
+    kept = None
     t0 = time.perf_counter()
     for s in range(0, n_sample, chunk):
-        _, G = oracle.real_sph(pts[s:s + chunk], L_MAX, NORMALIZE)
-        oracle.backward(G, gY[s:s + chunk])
+        Yr, G = oracle.real_sph(pts[s:s + chunk], L_MAX, NORMALIZE)
+        gr = oracle.backward(G, gY[s:s + chunk])
+        if s == 0:
+            kept = (Yr[idx], G[idx], gr[idx])
     dt = time.perf_counter() - t0
+
+    # the GPU's rows against the oracle's (inputs: the same float32 values)
+    Yg, dYg, gxg = gpu_rows(idx)
+    hp = pts[idx].astype(np.float64)
+    my, _ = oracle.per_l_errors(Yg, kept[0], hp, L_MAX, NORMALIZE, "Y")
+    md, _ = oracle.per_l_errors(dYg, kept[1], hp, L_MAX, NORMALIZE, "dY")
+    _, g, _ = oracle.component_scales(hp, L_MAX, NORMALIZE)
+    gYh = gY[idx].astype(np.float64)
+    mb = float((np.abs(gxg - np.asarray(kept[2], float)) / (np.abs(gYh) * g).sum(1)[:, None]).max())
+    acc = {"rows_checked": rows, "rows": f"{rows} random rows of the first {chunk}",
+           "Y_max_scaled_err": float(my.max()), "dY_max_scaled_err": float(md.max()),
+           "grad_xyz_max_scaled_err": mb, "tolerance": 1e-5}
     return {"value": n_sample / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
             "sample": f"first {n_sample} of the {N_POINTS} points, Y+dY and backward, "
-                      f"numpy longdouble recurrence tier, {dt:.1f} s wall, 1 thread"}
-
-
-def accuracy(xyz, Y, dY, gY, gx, rows: int = 2048):
-    import numpy as np
-    import torch
-
-    import oracle
-    rng = np.random.default_rng(7)
-    idx = np.sort(rng.choice(xyz.shape[0], rows, replace=False))
-    ii = torch.as_tensor(idx, device=xyz.device)
-    hp = xyz[ii].double().cpu().numpy()
-    Yr, Gr = oracle.real_sph(hp, L_MAX, NORMALIZE)
-    my, _ = oracle.per_l_errors(Y[ii].cpu().numpy(), Yr, hp, L_MAX, NORMALIZE, "Y")
-    md, _ = oracle.per_l_errors(dY[ii].cpu().numpy(), Gr, hp, L_MAX, NORMALIZE, "dY")
-    gYh = gY[ii].double().cpu().numpy()
-    ref = np.asarray(oracle.backward(Gr, gYh), float)
-    _, g, _ = oracle.component_scales(hp, L_MAX, NORMALIZE)
-    mb = float((np.abs(gx[ii].double().cpu().numpy() - ref) / (np.abs(gYh) * g).sum(1)[:, None]).max())
-    return {"rows_checked": rows, "Y_max_scaled_err": float(my.max()), "dY_max_scaled_err": float(md.max()),
-            "grad_xyz_max_scaled_err": mb, "tolerance": 1e-5}
+                      f"numpy longdouble recurrence tier, {dt:.1f} s wall, 1 thread"}, acc
 
 
 def _time(fn, reps: int, warm: int = 3) -> float:
@@ -253,7 +253,33 @@ def extras(dev):
     td = _time(lambda: sph.sph_double_backward(xb, gYb, vb, L3, True), 10)
     out["double_backward_l6_f32_4M"] = {"s": td, "points_per_s": n3 / td,
                                         "GB_per_s": n3 * 4 * (3 + K3 + 3 + K3 + 3) / td / 1e9}
-    del xb, gYb, vb
+    # ... and its first backward, from the forward's stored dY
+    Y3 = torch.empty((n3, K3), device=dev)
+    dY3 = torch.empty((n3, 3, K3), device=dev)
+    gx3 = torch.empty((n3, 3), device=dev)
+    sph.sph_compute_with_gradients(xb, L3, True, Y=Y3, dY=dY3)
+    tb3 = _time(lambda: sph.sph_backward(dY3, gYb, L3, grad_xyz=gx3), 10)
+    out["backward_l6_f32_4M"] = {"s": tb3, "points_per_s": n3 / tb3,
+                                 "GB_per_s": n3 * 4 * (4 * K3 + 3) / tb3 / 1e9}
+    del xb, gYb, vb, Y3, dY3, gx3
+    # plain method, CPU-sized: N = 1000, float64, l_max = 4 (launch-bound)
+    x1 = torch.as_tensor(standard_normal_points(1000, SEEDS["plain_cpu"]), dtype=torch.float64).to(dev)
+    t1 = _time(lambda: sph.sph_compute_with_gradients(x1, 4, True), 50)
+    out["plain_l4_f64_1000"] = {"forward_s": t1, "points_per_s": 1000 / t1}
+    # precision workload: l_max = 32, N = 200 000 (unit sphere, near the poles,
+    # radii 1e-6..1e3), float32 and float64; errors are checked by the tests
+    from workloads import precision_stress_points
+    pts5, _ = precision_stress_points(200_000, SEEDS["precision"])
+    n5, K5 = pts5.shape[0], 33 ** 2
+    p5 = {}
+    for dt5, w5, name in ((torch.float32, 4, "f32"), (torch.float64, 8, "f64")):
+        x5 = torch.as_tensor(pts5, dtype=dt5).to(dev)
+        Y5 = torch.empty((n5, K5), dtype=dt5, device=dev)
+        dY5 = torch.empty((n5, 3, K5), dtype=dt5, device=dev)
+        t5 = _time(lambda: sph.sph_compute_with_gradients(x5, 32, True, Y=Y5, dY=dY5), 5)
+        p5[name] = {"forward_s": t5, "points_per_s": n5 / t5, "GB_per_s": n5 * w5 * (3 + 4 * K5) / t5 / 1e9}
+        del x5, Y5, dY5
+    out["precision_l32_200k"] = p5
     # batched: 20 000 environments, fused forward + backward with dY, per l_max
     pts, offs = csr_environments(20_000, 8, 128, 0.5, 5.0, SEEDS["batched"])
     nb = int(offs[-1])
@@ -387,7 +413,6 @@ def main():
     copy_gbs = 2 * half.numel() * 4 * 10 / (e1.elapsed_time(e2) * 1e-3) / 1e9
     del big, half, half2
 
-    acc = accuracy(xyz, Y, dY, gY, gx)
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -409,13 +434,16 @@ def main():
         "kernels": {k: {kk: (round(vv, 7) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in per_kernel.items()},
         "ceilings_GB_per_s": {"torch_fill_write_only": round(fill_gbs, 1), "torch_copy": round(copy_gbs, 1)},
-        "accuracy": acc,
         "kernel_sources": kernel_hash(),
     }
     if not args.no_extras:
         out["extra"] = extras(dev)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
+        def gpu_rows(idx):
+            ii = torch.as_tensor(idx, device=dev)
+            return (Y[ii].double().cpu().numpy(), dY[ii].double().cpu().numpy(),
+                    gx[ii].double().cpu().numpy())
+        out["cpu_baseline"], out["accuracy"] = cpu_baseline(gpu_rows)
     print(json.dumps(out), flush=True)
 
 

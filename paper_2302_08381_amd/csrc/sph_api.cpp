@@ -355,7 +355,9 @@ int32_t sph_backward(const void* dY, const void* grad_Y, int64_t n, int32_t l_ma
   sph::BwdParams p{dY, grad_Y, n, static_cast<int32_t>(K), grad_xyz};
   const int64_t grid = ceil_div(n, ki.tile_points);
   if (grid > 0x7fffffff) return fail(SPH_ERR_INVALID, "n too large for one launch");
-  hipError_t e = launch(ki.fn, static_cast<unsigned>(grid), ki.block, 0, &p, static_cast<hipStream_t>(stream));
+  hipError_t e = ensure_lds(ki.fn, ki.lds_bytes);
+  if (e != hipSuccess) return device_fail(e, "hipFuncSetAttribute");
+  e = launch(ki.fn, static_cast<unsigned>(grid), ki.block, ki.lds_bytes, &p, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return device_fail(e, "backward launch");
   return ok();
 }

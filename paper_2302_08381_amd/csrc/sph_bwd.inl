@@ -29,6 +29,17 @@ template <typename T>
 constexpr int bwd_waves(int K) {
   return (std::is_same_v<T, float> && K <= bwd_chunk<T, 2>()) ? 2 : 1;
 }
+
+// LDS stride (elements per row) that holds every chunk of K columns for
+// blocks of NW waves: the rows of one whole-row chunk, or the odd width of
+// the balanced chunks.  The dynamic LDS of a block is 4 * 16 NW rows of it.
+template <typename T, int NW>
+__host__ __device__ constexpr int bwd_stride(int K) {
+  const int KC = bwd_chunk<T, NW>();
+  const int nch = (K + KC - 1) / KC;
+  const int ch = (K + nch - 1) / nch;
+  return nch == 1 ? row_stride<T>(K, true) : (ch | 1);
+}
 constexpr int kBwdBatch = 16;
 // Loads in flight per thread for a one-chunk tile (gY and dY together):
 // measured best at 32 for float (two-wave blocks) and 48 for double (one-wave
@@ -41,10 +52,10 @@ __global__ __launch_bounds__(kWave * NW) void k_bwd(BwdParams P) {
   constexpr int PP = 16 * NW;   // points per block
   constexpr int NT = kWave * NW;
   constexpr int KC = bwd_chunk<T, NW>();
-  constexpr int SC = KC + Vec16<T>::n;  // >= row_stride of any chunk
-  __shared__ __align__(16) T sg[PP * SC];
-  __shared__ __align__(16) T sd[3 * PP * SC];
+  extern __shared__ __align__(16) unsigned char smem[];
   const int K = P.K;
+  T* sg = reinterpret_cast<T*>(smem);            // PP rows
+  T* sd = sg + PP * bwd_stride<T, NW>(K);        // 3 PP rows
   const int lane = threadIdx.x;
   const int pl = lane >> 2;
   const int q = lane & 3;

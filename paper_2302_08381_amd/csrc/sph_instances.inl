@@ -184,8 +184,11 @@ KernelInfo SPH_CAT(SPH_CAT(SPH_CAT(SPH_CAT(SPH_CAT(fwd_derivs_, SPH_SUFFIX), _n)
 #else
 KernelInfo SPH_CAT(bwd_info_, SPH_SUFFIX)(int L) {
   if (!in_range(L)) return KernelInfo{nullptr, 0, 0, 0, 0};
-  const int nw = bwd_waves<T>((L + 1) * (L + 1));
-  return KernelInfo{tables().bwd[nw - 1], 0, 0, 16 * nw, kWave * nw};
+  const int K = (L + 1) * (L + 1);
+  const int nw = bwd_waves<T>(K);
+  const int stride = nw == 2 ? bwd_stride<T, 2>(K) : bwd_stride<T, 1>(K);
+  const size_t lds = sizeof(T) * static_cast<size_t>(4 * 16 * nw * stride);  // sized by K: small l_max fit more blocks
+  return KernelInfo{tables().bwd[nw - 1], lds, lds, 16 * nw, kWave * nw};
 }
 
 KernelInfo SPH_CAT(dbwd_info_, SPH_SUFFIX)(int L, int normalize) {
