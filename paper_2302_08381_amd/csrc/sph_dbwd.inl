@@ -211,12 +211,21 @@ __device__ __forceinline__ void dbwd_group(const Point<T>& pt, T vx, T vy, T vz,
 }
 
 // MM: m-extent bucket (l_max <= MM).  Dynamic LDS: 64 * stride(L) elements.
-template <typename T, int MM, bool NORM>
-__global__ __launch_bounds__(kWave) void k_dbwd(DbwdParams P) {
+// DS = 2 (one group of degrees only): a block of two waves on the 64-point
+// tile, wave h emitting degrees [0, LS) or [LS, l_max] of every point (LS
+// balances the columns; the branch is uniform per wave).  Both waves copy the
+// tiles, and wave 1 hands its Hessian sums to wave 0 through 3 * 64 more LDS
+// elements.  Twice the waves per CU at the same LDS for this VALU-heavy
+// kernel.
+template <typename T, int MM, bool NORM, int DS>
+__global__ __launch_bounds__(kWave * DS) void k_dbwd(DbwdParams P) {
   constexpr int B = kDbwdBudget<T>;
+  constexpr int NT = kWave * DS;
   extern __shared__ __align__(16) unsigned char smem[];
   T* st = reinterpret_cast<T*>(smem);
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid % kWave;
+  const int half = tid / kWave;
   const int L = P.L;
   const int K = (L + 1) * (L + 1);
   const int64_t p0 = static_cast<int64_t>(blockIdx.x) * kWave;
@@ -236,22 +245,50 @@ __global__ __launch_bounds__(kWave) void k_dbwd(DbwdParams P) {
   const Point<T> pt = make_point<T, NORM>(x, y, z);
   const bool write_gg = P.ggY != nullptr;
   DbwdAcc<T> A{T(0), T(0), T(0)};
-  for (int la = 0; la <= L;) {
-    const int lb = group_end(la, L, B);
-    const int kb = la * la;
-    const int cnt = lb * lb - kb;
-    const int S = row_stride<T>(cnt, cnt == K);
-    const T* src = static_cast<const T*>(P.gY) + p0 * K + kb;
-    copy_in(st, S, src, K, cnt, np, lane, aligned16(src));
+  if constexpr (DS == 2) {
+    const int S = row_stride<T>(K, true);
+    int LS = 1;  // smallest degree with LS^2 >= K / 2
+    while (LS <= L && 2 * LS * LS < K) ++LS;
+    const T* src = static_cast<const T*>(P.gY) + p0 * K;
+    copy_in<NT>(st, S, src, K, K, np, tid, aligned16(src));
     __syncthreads();
-    dbwd_group<T, MM, NORM>(pt, vx, vy, vz, la, lb, kb, S, st, write_gg, A, lane);
+    if (half == 0)
+      dbwd_group<T, MM, NORM>(pt, vx, vy, vz, 0, LS, 0, S, st, write_gg, A, lane);
+    else
+      dbwd_group<T, MM, NORM>(pt, vx, vy, vz, LS, L + 1, 0, S, st, write_gg, A, lane);
+    T* sacc = st + kWave * S;
+    if (half == 1) {
+      sacc[lane] = A.hx;
+      sacc[kWave + lane] = A.hy;
+      sacc[2 * kWave + lane] = A.hz;
+    }
     __syncthreads();
     if (write_gg) {
-      T* dst = static_cast<T*>(P.ggY) + p0 * K + kb;
-      copy_out(st, S, dst, K, cnt, np, lane, aligned16(dst));
-      __syncthreads();
+      T* dst = static_cast<T*>(P.ggY) + p0 * K;
+      copy_out<NT>(st, S, dst, K, K, np, tid, aligned16(dst));
     }
-    la = lb;
+    if (half == 1) return;
+    A.hx += sacc[lane];
+    A.hy += sacc[kWave + lane];
+    A.hz += sacc[2 * kWave + lane];
+  } else {
+    for (int la = 0; la <= L;) {
+      const int lb = group_end(la, L, B);
+      const int kb = la * la;
+      const int cnt = lb * lb - kb;
+      const int S = row_stride<T>(cnt, cnt == K);
+      const T* src = static_cast<const T*>(P.gY) + p0 * K + kb;
+      copy_in(st, S, src, K, cnt, np, lane, aligned16(src));
+      __syncthreads();
+      dbwd_group<T, MM, NORM>(pt, vx, vy, vz, la, lb, kb, S, st, write_gg, A, lane);
+      __syncthreads();
+      if (write_gg) {
+        T* dst = static_cast<T*>(P.ggY) + p0 * K + kb;
+        copy_out(st, S, dst, K, cnt, np, lane, aligned16(dst));
+        __syncthreads();
+      }
+      la = lb;
+    }
   }
   if (P.gxyz2 != nullptr && lane < np) {
     T s = T(1);

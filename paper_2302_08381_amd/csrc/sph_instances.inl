@@ -98,18 +98,33 @@ struct Tables {
 };
 
 #else
-template <bool NORM, int... Is>
+// Double backward: one wave per 64-point tile, or (one group of degrees:
+// l_max <= 12 float, <= 8 double) the degree-split block of two waves.
+constexpr int kDbwdSplitMax = std::is_same_v<T, float> ? 12 : 8;
+
+template <bool NORM, int MM, int DS>
+const void* dbwd_ptr() {
+  if constexpr (DS == 2 && MM > kDbwdSplitMax)
+    return nullptr;
+  else
+    return reinterpret_cast<const void*>(&k_dbwd<T, MM, NORM, DS>);
+}
+
+template <bool NORM, int DS, int... Is>
 void fill_dbwd(const void** out, std::integer_sequence<int, Is...>) {
-  const void* tbl[] = {reinterpret_cast<const void*>(&k_dbwd<T, kBuckets[Is], NORM>)...};
+  const void* tbl[] = {dbwd_ptr<NORM, kBuckets[Is], DS>()...};
   for (size_t i = 0; i < sizeof...(Is); ++i) out[i] = tbl[i];
 }
 
 struct Tables {
   const void* dbwd[2][kNumBuckets];
+  const void* dbwd_split[2][kNumBuckets];
   const void* bwd[2];  // one and two waves per block
   Tables() {
-    fill_dbwd<false>(dbwd[0], Buckets{});
-    fill_dbwd<true>(dbwd[1], Buckets{});
+    fill_dbwd<false, 1>(dbwd[0], Buckets{});
+    fill_dbwd<true, 1>(dbwd[1], Buckets{});
+    fill_dbwd<false, 2>(dbwd_split[0], Buckets{});
+    fill_dbwd<true, 2>(dbwd_split[1], Buckets{});
     bwd[0] = reinterpret_cast<const void*>(&k_bwd<T, 1>);
     bwd[1] = reinterpret_cast<const void*>(&k_bwd<T, 2>);
   }
@@ -194,6 +209,10 @@ KernelInfo SPH_CAT(bwd_info_, SPH_SUFFIX)(int L) {
 KernelInfo SPH_CAT(dbwd_info_, SPH_SUFFIX)(int L, int normalize) {
   if (!in_range(L) || (normalize != 0 && normalize != 1)) return KernelInfo{nullptr, 0, 0, 0, 0};
   const size_t lds = sizeof(T) * kWave * static_cast<size_t>(tile_stride<T>(L, kDbwdBudget<T>));
+  const bool one_group = group_end(0, L, kDbwdBudget<T>) > L;
+  const void* split = tables().dbwd_split[normalize][bucket_index(L)];
+  if (one_group && split != nullptr)  // + wave 1's Hessian sums
+    return KernelInfo{split, lds + 3 * kWave * sizeof(T), lds + 3 * kWave * sizeof(T), kWave, 2 * kWave};
   return KernelInfo{tables().dbwd[normalize][bucket_index(L)], lds, lds, kWave, kWave};
 }
 #endif
