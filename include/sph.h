@@ -190,10 +190,12 @@ int32_t sph_batched_get_config(int32_t l_max, int32_t normalize, int32_t dtype,
  *   blocks_per_cu  0 .. 64 (0: one tile per block)
  * Returns SPH_ERR_INVALID for an unknown combination, a variant that does
  * not exist for it, or an out of range blocks_per_cu; SPH_ERR_LMAX for l_max
- * out of range.  With dY or the backward, tile16 and runtime_degree exist
- * wherever the default is unrolled (float l_max <= 12, double l_max <= 8)
- * and degree_split for float 9 <= l_max <= 12 and double 4 <= l_max <= 8;
- * a variant may name the default kernel.  Values only: runtime_degree only.
+ * out of range.  With dY or the backward: tile16 exists wherever the
+ * default is unrolled (float l_max <= 12, double l_max <= 8),
+ * runtime_degree for every l_max, degree_split for float 9 <= l_max <= 12,
+ * double 4 <= l_max <= 8 and, without the backward, every larger l_max; a
+ * variant may name the default kernel.  Values only: runtime_degree where
+ * the default is unrolled.
  */
 int32_t sph_batched_set_config(int32_t l_max, int32_t normalize, int32_t dtype,
                                int32_t store_dY, int32_t with_backward,

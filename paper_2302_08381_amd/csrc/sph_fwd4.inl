@@ -252,6 +252,37 @@ __device__ __forceinline__ void fwd4_group(const Role<T>& ro, const Point<T>& pt
   __syncthreads();
 }
 
+// A group of degrees [la, lb) of a run-time l_max with its degrees split
+// between the block's two waves at the degree that balances the columns:
+// wave h emits [la, ls) or [ls, lb) of every point (uniform per wave), both
+// store the group.  Values and derivatives only (no fused backward).
+template <typename T, int MM, bool NORM, bool STORE>
+__device__ __forceinline__ void fwd4_group_split_rt(const Role<T>& ro, const Point<T>& pt, int la, int lb, int K,
+                                                    int64_t p0, int np, int tid, int half, int lrow,
+                                                    const FwdParams& P, T* st) {
+  constexpr int PT = kQuadWavePoints;
+  constexpr int NT = 2 * kWave;
+  const int kb = la * la;
+  const int cnt = lb * lb - kb;
+  const int S = row_stride<T>(cnt, cnt == K);
+  int ls = la + 1;  // first degree of wave 1
+  while (ls < lb && 2 * (ls * ls - kb) < cnt) ++ls;
+  if (half == 0)
+    emit4<T, MM, NORM, false>(ro, pt, la, ls, st + lrow * S - kb);
+  else
+    emit4<T, MM, NORM, false>(ro, pt, ls, lb, st + lrow * S - kb);
+  __syncthreads();
+  {
+    T* dst = static_cast<T*>(P.Y) + p0 * K + kb;
+    copy_out<NT>(st, S, dst, K, cnt, np, tid, aligned16(dst));
+  }
+  if constexpr (STORE) {
+    T* dst = static_cast<T*>(P.dY) + p0 * 3 * K + kb;
+    copy_out<NT>(st + PT * S, S, dst, K, cnt, 3 * np, tid, aligned16(dst));
+  }
+  __syncthreads();
+}
+
 // One compile-time group of degrees [LA, LB).  FAST: a full tile of
 // a one-group plan with 16-byte aligned outputs, copied out with the
 // fixed-size unpredicated copy; otherwise the general copy.
@@ -422,7 +453,8 @@ constexpr bool quad_has_fast() {
 // take a separate general path.
 template <typename T, int MM, int LT, bool NORM, bool FUSED, bool STORE, int NW, int DS>
 __global__ __launch_bounds__(kWave * NW * DS) void k_fwd4(FwdParams P) {
-  static_assert(DS == 1 || (DS == 2 && NW == 1 && LT >= 0), "degree split: one-wave tiles, compile-time l_max");
+  static_assert(DS == 1 || (DS == 2 && NW == 1 && (LT >= 0 || !FUSED)),
+                "degree split: one-wave tiles; run-time l_max without the fused backward");
   constexpr int PT = kQuadWavePoints * NW;  // points per tile
   constexpr int NQ = kWave * NW;            // quad lanes: four per point, also the tile's rows
   constexpr int B = kQuadBudget<T>;
@@ -450,7 +482,13 @@ __global__ __launch_bounds__(kWave * NW * DS) void k_fwd4(FwdParams P) {
     const Point<T> pt = make_point<T, NORM>(x, y, z);
     const Role<T> ro = make_role<T, NORM>(r, pt);
     T acc = T(0);
-    if constexpr (DS == 2) {
+    if constexpr (DS == 2 && LT < 0) {
+      for (int la = 0; la <= L;) {
+        const int lb = group_end(la, L, B);
+        fwd4_group_split_rt<T, MM, NORM, STORE>(ro, pt, la, lb, K, p0, np, tid, half, lrow, P, st);
+        la = lb;
+      }
+    } else if constexpr (DS == 2) {
       static_assert(make_plan(LT, B).ng == 1, "degree split needs one group of degrees");
       fwd4_tile_split<T, MM, NORM, FUSED, STORE, FAST, LT>(ro, pt, p0, np, tid, half, lane, lrow, P, st, sg, sacc,
                                                            acc);

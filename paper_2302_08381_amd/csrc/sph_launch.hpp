@@ -66,12 +66,14 @@ struct KernelInfo {
 //   kVarDefault  the compile-time (unrolled) kernel where one exists, on its
 //                default tile (32 points on two waves for float l_max <= 8,
 //                the degree-split tile where that measured faster, else 16
-//                points on one wave), else the run-time-degree kernel
+//                points on one wave), else the run-time-degree kernel (with
+//                each group's degrees split between two waves unless the
+//                backward is fused)
 //   kVarTile16   the compile-time kernel on an unsplit 16-point, one-wave tile
-//   kVarRuntime  the run-time-degree (not unrolled) kernel where the default
-//                is a compile-time one
-//   kVarSplit    the compile-time kernel on a 16-point tile whose degrees are
-//                split between two waves (float l_max 9..12, double 4..8)
+//   kVarRuntime  the unsplit run-time-degree (not unrolled) kernel
+//   kVarSplit    a degree-split kernel: the compile-time one (float l_max
+//                9..12, double 4..8) or the run-time-degree one (larger
+//                l_max, no fused backward)
 enum DerivMode { kDerivStore = 0, kDerivFusedStore = 1, kDerivFused = 2, kNumDerivModes = 3 };
 enum FwdVariant { kVarDefault = 0, kVarTile16 = 1, kVarRuntime = 2, kVarSplit = 3, kNumFwdVariants = 4 };
 KernelInfo fwd_values_f32_n0(int L, int variant);

@@ -121,4 +121,5 @@ def test_set_config_validation(lib):
     assert c(13, 1, 0, 1, 1, 1, 0) == 2        # tile16 does not exist past the unrolled kernels
     assert c(9, 1, 1, 1, 1, 1, 0) == 2         # ... (double: l_max <= 8)
     assert c(8, 1, 0, 0, 0, 1, 0) == 2         # ... nor for the values-only kernel
-    assert c(20, 1, 0, 1, 1, 2, 0) == 2        # runtime_degree is already the default at l_max = 20
+    assert c(20, 1, 0, 0, 0, 2, 0) == 2        # values only: runtime_degree is the default at l_max = 20
+    assert c(20, 1, 0, 1, 1, 3, 0) == 2        # no degree split with the fused backward past l_max = 12
