@@ -62,6 +62,7 @@ struct Vec16<double> {
 // still.  The buffer resource covers [base, base + bytes); the hardware drops
 // any store past its end.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 constexpr int kStreamStorePolicy = 16 | 2;  // sc1 | nt
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t stream_rsrc(void* base, int bytes) {
@@ -379,6 +380,59 @@ __device__ __forceinline__ void copy_out(const T* __restrict__ st, int S, T* __r
         if (i0 + u * NT < nv) stream_store16(v[u], rs, (i0 + u * NT) * 16);
     }
     for (int j = nv * W + lane; j < total; j += NT) __builtin_nontemporal_store(st[j], dst + j);
+    return;
+  }
+  if (gstride != cnt && cnt >= 2 * W) {
+    // Partial rows (one group of degrees).  Every row segment holds at least
+    // M = floor((cnt - W + 1) / W) whole aligned 16-byte vectors, starting
+    // after its head (the elements before its first aligned one); they leave
+    // with 16-byte stores.  The other R = cnt - W M elements of the row (its
+    // head and its tail) leave one by one.  Default cache policy: L2 merges
+    // the partial lines at segment ends.  All stores go through a buffer
+    // resource that covers exactly the rows' span.
+    using V = typename Vec16<T>::type;
+    const int M = (cnt - (W - 1)) / W;
+    const int R = cnt - W * M;
+    const int a0 = static_cast<int>((reinterpret_cast<uintptr_t>(dst) / sizeof(T)) % W);
+    const int gm = gstride % W;
+    const __amdgpu_buffer_rsrc_t rsr = stream_rsrc(dst, static_cast<int>(((rows - 1) * gstride + cnt) * sizeof(T)));
+    {
+      int r = lane / M, j = lane - r * M;
+      const int qs = NT / M, rq = NT - qs * M;
+      for (int i = lane; i < rows * M; i += NT) {
+        const int c0 = (W - (a0 + r * gm) % W) % W + W * j;  // first column of the vector
+        V v;
+#pragma unroll
+        for (int t = 0; t < W; ++t) v[t] = st[r * S + c0 + t];
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rsr,
+                                               static_cast<int>((r * gstride + c0) * sizeof(T)), 0, 0);
+        r += qs;
+        j += rq;
+        if (j >= M) {
+          j -= M;
+          ++r;
+        }
+      }
+    }
+    {
+      int r = lane / R, e = lane - r * R;
+      const int qs = NT / R, rq = NT - qs * R;
+      for (int i = lane; i < rows * R; i += NT) {
+        const int head = (W - (a0 + r * gm) % W) % W;
+        const int c = e < head ? e : e + W * M;  // the head, then the tail after the middle
+        const int off = static_cast<int>((r * gstride + c) * sizeof(T));
+        if constexpr (sizeof(T) == 4)
+          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, st[r * S + c]), rsr, off, 0, 0);
+        else
+          __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, st[r * S + c]), rsr, off, 0, 0);
+        r += qs;
+        e += rq;
+        if (e >= R) {
+          e -= R;
+          ++r;
+        }
+      }
+    }
     return;
   }
   int p = lane / cnt;

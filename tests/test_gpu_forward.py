@@ -8,7 +8,7 @@ import torch
 import oracle
 from workloads import SEEDS, precision_stress_points, standard_normal_points
 
-from _gpu_common import TOL, assert_close_per_l, host_points, to_dev
+from _gpu_common import TOL, assert_bitwise_equal, assert_close_per_l, host_points, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -173,3 +173,35 @@ def test_every_tile_written_for_grids_of_any_size(dtype):
         assert_close_per_l(Y.cpu().numpy(), Yr, hp, 8, True, "Y", TOL[dtype])
         assert_close_per_l(dY.cpu().numpy(), Gr, hp, 8, True, "dY", TOL[dtype])
         assert_close_per_l(Yv.cpu().numpy(), Yr, hp, 8, True, "Y", TOL[dtype])
+
+
+@pytest.mark.parametrize("dtype,l_max", [(torch.float32, 16), (torch.float32, 32), (torch.float64, 12)])
+def test_groups_of_degrees_with_misaligned_outputs(dtype, l_max):
+    """l_max past one group of degrees: partial rows leave with 16-byte stores
+    of their aligned middles.  Outputs 1..3 elements past a 16-byte boundary
+    (every head length) must equal the aligned outputs bitwise."""
+    import paper_2302_08381_amd as sph
+    n = 150  # several tiles and a ragged tail
+    K = (l_max + 1) ** 2
+    xyz = to_dev(standard_normal_points(n, 900 + l_max), dtype)
+    Y0, dY0 = sph.sph_compute_with_gradients(xyz, l_max, True)
+    Yv0 = sph.sph_compute(xyz, l_max, True)
+    for shift in (1, 2, 3):
+        print(f"misaligned outputs l_max={l_max} dtype={dtype} shift={shift}", flush=True)
+        bY = torch.full((n * K + shift,), float("nan"), dtype=dtype, device="cuda")
+        bdY = torch.full((n * 3 * K + shift,), float("nan"), dtype=dtype, device="cuda")
+        Y = bY[shift:].view(n, K)
+        dY = bdY[shift:].view(n, 3, K)
+        sph.sph_compute_with_gradients(xyz, l_max, True, Y=Y, dY=dY)
+        bv = torch.full((n * K + shift,), float("nan"), dtype=dtype, device="cuda")
+        Yv = bv[shift:].view(n, K)
+        sph.sph_compute(xyz, l_max, True, Y=Yv)
+        torch.cuda.synchronize()
+        assert_bitwise_equal(Y, Y0, "Y")
+        assert_bitwise_equal(dY, dY0, "dY")
+        assert_bitwise_equal(Yv, Yv0, "values-only Y")
+        assert torch.isnan(bY[:shift]).all() and torch.isnan(bdY[:shift]).all()  # nothing written before
+    hp = host_points(xyz)
+    Yr, Gr = oracle.real_sph(hp, l_max, True)
+    assert_close_per_l(Y0.cpu().numpy(), Yr, hp, l_max, True, "Y", TOL[dtype])
+    assert_close_per_l(dY0.cpu().numpy(), Gr, hp, l_max, True, "dY", TOL[dtype])
