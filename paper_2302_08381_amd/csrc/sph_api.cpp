@@ -136,6 +136,27 @@ hipError_t launch(const void* fn, unsigned grid, unsigned block, size_t lds, voi
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Blocks of a kernel that are resident on one CU at once (from the runtime's
+// occupancy for this block size and LDS), cached per device and kernel.  A
+// loop-over-tiles grid must not exceed this times the CUs: blocks beyond it
+// wait for a whole round.
+std::mutex g_occ_mu;
+std::map<std::tuple<int, const void*, int, size_t>, int> g_occ;
+
+int resident_per_cu(const void* fn, int block, size_t lds) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  std::lock_guard<std::mutex> lk(g_occ_mu);
+  const auto key = std::make_tuple(dev, fn, block, lds);
+  auto it = g_occ.find(key);
+  if (it != g_occ.end()) return it->second;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, lds) != hipSuccess || per_cu <= 0) per_cu = 1;
+  (void)hipGetLastError();
+  g_occ[key] = per_cu;
+  return per_cu;
+}
+
 // Grid of a plain forward call: one tile per block.  Blocks that each write
 // one tile and exit keep the chip's concurrent stores on a compact, advancing
 // address range; a resident grid of blocks looping over tiles spreads them
@@ -353,10 +374,12 @@ int32_t sph_backward(const void* dY, const void* grad_Y, int64_t n, int32_t l_ma
   const sph::KernelInfo ki = bwd_info(dtype, l_max);
   if (ki.fn == nullptr) return fail(SPH_ERR_INVALID, "no kernel for these arguments");
   sph::BwdParams p{dY, grad_Y, n, static_cast<int32_t>(K), grad_xyz};
-  const int64_t grid = ceil_div(n, ki.tile_points);
-  if (grid > 0x7fffffff) return fail(SPH_ERR_INVALID, "n too large for one launch");
   hipError_t e = ensure_lds(ki.fn, ki.lds_bytes);
   if (e != hipSuccess) return device_fail(e, "hipFuncSetAttribute");
+  int64_t grid = ceil_div(n, ki.tile_points);
+  if (ki.blocks_per_cu > 0)  // a resident grid looping over tiles
+    grid = std::min<int64_t>(grid, int64_t(num_cus()) * resident_per_cu(ki.fn, ki.block, ki.lds_bytes));
+  if (grid > 0x7fffffff) return fail(SPH_ERR_INVALID, "n too large for one launch");
   e = launch(ki.fn, static_cast<unsigned>(grid), ki.block, ki.lds_bytes, &p, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return device_fail(e, "backward launch");
   return ok();

@@ -59,52 +59,105 @@ __global__ __launch_bounds__(kWave * NW) void k_bwd(BwdParams P) {
   const int lane = threadIdx.x;
   const int pl = lane >> 2;
   const int q = lane & 3;
-  // plain block order: the XCD-contiguous order of the forward reads slower here
-  const int64_t p0 = static_cast<int64_t>(blockIdx.x) * PP;
-  if (p0 >= P.n) return;
-  const int np = static_cast<int>(P.n - p0 < PP ? P.n - p0 : PP);
-  const T* gY = static_cast<const T*>(P.gY) + p0 * K;
-  const T* dY = static_cast<const T*>(P.dY) + p0 * 3 * K;
   const int nch = (K + KC - 1) / KC;
   const int ch = (K + nch - 1) / nch;  // balanced chunk width, <= KC
 
-  T a0 = T(0), a1 = T(0), a2 = T(0);
-  for (int kc0 = 0; kc0 < K; kc0 += ch) {
-    const int cnt = (K - kc0) < ch ? (K - kc0) : ch;
-    const int S = row_stride<T>(cnt, cnt == K);
-    if (cnt == K && S == K && aligned16(gY) && aligned16(dY)) {
-      // one chunk of whole rows: the gY and dY blocks share the round trips
-      copy_in_pair<NT, kBwdPairBatch<T>>(sg, gY, np * K, sd, dY, 3 * np * K, lane);
-    } else {
-      copy_in<NT, kBwdBatch>(sg, S, gY + kc0, K, cnt, np, lane, aligned16(gY + kc0));
-      copy_in<NT, kBwdBatch>(sd, S, dY + kc0, K, cnt, 3 * np, lane, aligned16(dY + kc0));
-    }
-    __syncthreads();
-    if (pl < np) {
-      const T* g = sg + pl * S;
-      const T* d0 = sd + (3 * pl) * S;
-      const T* d1 = d0 + S;
-      const T* d2 = d1 + S;
+  // sum over columns k = q (mod 4) of point pl, then over the four lanes
+  auto reduce = [&](int S, int cnt, T& a0, T& a1, T& a2) {
+    const T* g = sg + pl * S;
+    const T* d0 = sd + (3 * pl) * S;
+    const T* d1 = d0 + S;
+    const T* d2 = d1 + S;
 #pragma unroll 4
-      for (int k = q; k < cnt; k += 4) {
-        const T gv = g[k];
-        a0 += gv * d0[k];
-        a1 += gv * d1[k];
-        a2 += gv * d2[k];
-      }
+    for (int k = q; k < cnt; k += 4) {
+      const T gv = g[k];
+      a0 += gv * d0[k];
+      a1 += gv * d1[k];
+      a2 += gv * d2[k];
     }
-    __syncthreads();
+  };
+  auto finish = [&](int64_t p0, int np, T a0, T a1, T a2) {
+    a0 += __shfl_xor(a0, 1);
+    a1 += __shfl_xor(a1, 1);
+    a2 += __shfl_xor(a2, 1);
+    a0 += __shfl_xor(a0, 2);
+    a1 += __shfl_xor(a1, 2);
+    a2 += __shfl_xor(a2, 2);
+    if (pl < np && q < 3) {
+      const T v = (q == 0) ? a0 : (q == 1 ? a1 : a2);
+      static_cast<T*>(P.gxyz)[(p0 + pl) * 3 + q] = v;
+    }
+  };
+  // one tile, any shape: chunks of columns through LDS
+  auto general_tile = [&](int64_t p0) {
+    const int np = static_cast<int>(P.n - p0 < PP ? P.n - p0 : PP);
+    const T* gY = static_cast<const T*>(P.gY) + p0 * K;
+    const T* dY = static_cast<const T*>(P.dY) + p0 * 3 * K;
+    T a0 = T(0), a1 = T(0), a2 = T(0);
+    for (int kc0 = 0; kc0 < K; kc0 += ch) {
+      const int cnt = (K - kc0) < ch ? (K - kc0) : ch;
+      const int S = row_stride<T>(cnt, cnt == K);
+      if (cnt == K && S == K && aligned16(gY) && aligned16(dY)) {
+        // one chunk of whole rows: the gY and dY blocks share the round trips
+        copy_in_pair<NT, kBwdPairBatch<T>>(sg, gY, np * K, sd, dY, 3 * np * K, lane);
+      } else {
+        copy_in<NT, kBwdBatch>(sg, S, gY + kc0, K, cnt, np, lane, aligned16(gY + kc0));
+        copy_in<NT, kBwdBatch>(sd, S, dY + kc0, K, cnt, 3 * np, lane, aligned16(dY + kc0));
+      }
+      __syncthreads();
+      if (pl < np) reduce(S, cnt, a0, a1, a2);
+      __syncthreads();
+    }
+    finish(p0, np, a0, a1, a2);
+  };
+
+  // Double: full tiles of one contiguous chunk whose gY and dY fit one
+  // register batch (the block's 16-byte vectors, nva + nvb <= NT * NB) run a
+  // loop over tiles (the host launches a resident grid) that loads tile t + G
+  // into registers while it reduces tile t from LDS, so the loads stay in
+  // flight across tiles: 514 -> 437 us at l_max = 8, N = 1e6.  For float the
+  // second register batch costs half the resident blocks, so float keeps one
+  // tile per block.
+  using V = typename Vec16<T>::type;
+  constexpr int W = Vec16<T>::n;
+  constexpr int NB = kBwdPairBatch<T>;
+  constexpr bool kPipe = !std::is_same_v<T, float>;
+  const int nva = PP * K / W, nvb = 3 * nva, nv = nva + nvb;
+  const int64_t nfull = P.n / PP;
+  const bool pipe = kPipe && K <= KC && row_stride<T>(K, true) == K && (PP * K) % W == 0 && nv <= NT * NB &&
+                    aligned16(P.gY) && aligned16(P.dY);
+  int64_t tile = blockIdx.x;
+  if constexpr (kPipe) {
+   if (pipe) {
+    V v[NB];
+    auto issue = [&](int64_t t) {
+      const V* ga = reinterpret_cast<const V*>(static_cast<const T*>(P.gY) + t * PP * K);
+      const V* gb = reinterpret_cast<const V*>(static_cast<const T*>(P.dY) + t * PP * 3 * K);
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int i = lane + u * NT;
+        if (i < nv) v[u] = __builtin_nontemporal_load(i < nva ? ga + i : gb + (i - nva));
+      }
+    };
+    V* la = reinterpret_cast<V*>(sg);
+    V* lb = reinterpret_cast<V*>(sd);
+    if (tile < nfull) issue(tile);
+    for (; tile < nfull; tile += gridDim.x) {
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int i = lane + u * NT;
+        if (i < nv) *(i < nva ? la + i : lb + (i - nva)) = v[u];
+      }
+      __syncthreads();
+      if (tile + gridDim.x < nfull) issue(tile + gridDim.x);
+      T a0 = T(0), a1 = T(0), a2 = T(0);
+      reduce(K, K, a0, a1, a2);
+      finish(tile * PP, PP, a0, a1, a2);
+      __syncthreads();
+    }
+   }
   }
-  a0 += __shfl_xor(a0, 1);
-  a1 += __shfl_xor(a1, 1);
-  a2 += __shfl_xor(a2, 1);
-  a0 += __shfl_xor(a0, 2);
-  a1 += __shfl_xor(a1, 2);
-  a2 += __shfl_xor(a2, 2);
-  if (pl < np && q < 3) {
-    const T v = (q == 0) ? a0 : (q == 1 ? a1 : a2);
-    static_cast<T*>(P.gxyz)[(p0 + pl) * 3 + q] = v;
-  }
+  for (; tile * PP < P.n; tile += gridDim.x) general_tile(tile * PP);
 }
 
 }  // namespace sph

@@ -227,7 +227,9 @@ KernelInfo SPH_CAT(bwd_info_, SPH_SUFFIX)(int L) {
   const int nw = bwd_waves<T>(K);
   const int stride = nw == 2 ? bwd_stride<T, 2>(K) : bwd_stride<T, 1>(K);
   const size_t lds = sizeof(T) * static_cast<size_t>(4 * 16 * nw * stride);  // sized by K: small l_max fit more blocks
-  return KernelInfo{tables().bwd[nw - 1], lds, lds, 16 * nw, kWave * nw};
+  // double: a resident grid for the pipelined loop over tiles
+  const int bpc = std::is_same_v<T, float> ? 0 : 1;
+  return KernelInfo{tables().bwd[nw - 1], lds, lds, 16 * nw, kWave * nw, bpc};
 }
 
 KernelInfo SPH_CAT(dbwd_info_, SPH_SUFFIX)(int L, int normalize) {

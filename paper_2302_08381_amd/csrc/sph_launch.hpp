@@ -54,6 +54,7 @@ struct KernelInfo {
   size_t lds_bytes_bwd;
   int tile_points;
   int block;
+  int blocks_per_cu = 0;  // plain calls: 1: a resident grid (occupancy x CUs) loops over tiles; 0: one tile per block
 };
 
 // Per element type (suffix f32 / f64) and normalisation; fn == nullptr when
