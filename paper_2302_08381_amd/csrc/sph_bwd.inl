@@ -46,9 +46,17 @@ constexpr int kBwdBatch = 16;
 // blocks, 40.5 vectors per thread at l_max = 8); other depths are slower.
 template <typename T>
 inline constexpr int kBwdPairBatch = std::is_same_v<T, float> ? 32 : 48;
+// The pipelined loop over tiles (see k_bwd): float two-wave blocks (20.25
+// vectors per thread at l_max = 8, batches of 24 and two waves per SIMD, no
+// spills) and double one-wave blocks (batches of 48).
+template <typename T, int NW>
+inline constexpr bool kBwdPipe = !std::is_same_v<T, float> || NW == 2;
+template <typename T>
+inline constexpr int kBwdPipeBatch = std::is_same_v<T, float> ? 24 : 48;
 
 template <typename T, int NW>
-__global__ __launch_bounds__(kWave * NW) void k_bwd(BwdParams P) {
+__global__ __launch_bounds__(kWave * NW)
+__attribute__((amdgpu_waves_per_eu(std::is_same_v<T, float> && kBwdPipe<T, NW> ? 2 : 1))) void k_bwd(BwdParams P) {
   constexpr int PP = 16 * NW;   // points per block
   constexpr int NT = kWave * NW;
   constexpr int KC = bwd_chunk<T, NW>();
@@ -99,7 +107,9 @@ __global__ __launch_bounds__(kWave * NW) void k_bwd(BwdParams P) {
       const int S = row_stride<T>(cnt, cnt == K);
       if (cnt == K && S == K && aligned16(gY) && aligned16(dY)) {
         // one chunk of whole rows: the gY and dY blocks share the round trips
-        copy_in_pair<NT, kBwdPairBatch<T>>(sg, gY, np * K, sd, dY, 3 * np * K, lane);
+        // (where the pipelined loop exists this is only the ragged last tile:
+        // a small batch keeps the kernel's registers for the loop)
+        copy_in_pair<NT, kBwdPipe<T, NW> ? 8 : kBwdPairBatch<T>>(sg, gY, np * K, sd, dY, 3 * np * K, lane);
       } else {
         copy_in<NT, kBwdBatch>(sg, S, gY + kc0, K, cnt, np, lane, aligned16(gY + kc0));
         copy_in<NT, kBwdBatch>(sd, S, dY + kc0, K, cnt, 3 * np, lane, aligned16(dY + kc0));
@@ -111,17 +121,17 @@ __global__ __launch_bounds__(kWave * NW) void k_bwd(BwdParams P) {
     finish(p0, np, a0, a1, a2);
   };
 
-  // Double: full tiles of one contiguous chunk whose gY and dY fit one
-  // register batch (the block's 16-byte vectors, nva + nvb <= NT * NB) run a
-  // loop over tiles (the host launches a resident grid) that loads tile t + G
-  // into registers while it reduces tile t from LDS, so the loads stay in
-  // flight across tiles: 514 -> 437 us at l_max = 8, N = 1e6.  For float the
-  // second register batch costs half the resident blocks, so float keeps one
-  // tile per block.
+  // Full tiles of one contiguous chunk whose gY and dY fit one register batch
+  // (the block's 16-byte vectors, nva + nvb <= NT * NB) run a loop over tiles
+  // (the host launches a resident grid) that loads tile t + G into registers
+  // while it reduces tile t from LDS, so the loads stay in flight across
+  // tiles.  N = 1e6, l_max = 8: double 514 -> 437 us on the resident grid;
+  // float 226 -> 202 us at one tile per block (the batch in registers, then
+  // one commit to LDS, against the batched copy of general_tile).
   using V = typename Vec16<T>::type;
   constexpr int W = Vec16<T>::n;
-  constexpr int NB = kBwdPairBatch<T>;
-  constexpr bool kPipe = !std::is_same_v<T, float>;
+  constexpr int NB = kBwdPipeBatch<T>;
+  constexpr bool kPipe = kBwdPipe<T, NW>;
   const int nva = PP * K / W, nvb = 3 * nva, nv = nva + nvb;
   const int64_t nfull = P.n / PP;
   const bool pipe = kPipe && K <= KC && row_stride<T>(K, true) == K && (PP * K) % W == 0 && nv <= NT * NB &&
@@ -143,6 +153,11 @@ __global__ __launch_bounds__(kWave * NW) void k_bwd(BwdParams P) {
     V* lb = reinterpret_cast<V*>(sd);
     if (tile < nfull) issue(tile);
     for (; tile < nfull; tile += gridDim.x) {
+      // Wait for the whole batch once, on every path: with the waits left to
+      // the compiler, the stores below (each under its own lane condition)
+      // leave the batch possibly in flight on the skipped paths, and every
+      // load of the next batch then waits for all loads before it.
+      __builtin_amdgcn_s_waitcnt(kWaitVmem0);
 #pragma unroll
       for (int u = 0; u < NB; ++u) {
         const int i = lane + u * NT;

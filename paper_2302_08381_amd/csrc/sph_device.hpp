@@ -26,6 +26,10 @@
 namespace sph {
 
 constexpr int kWave = 64;
+// s_waitcnt operand (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt in
+// 6:4, lgkmcnt in 11:8) that waits for every vector-memory access and leaves
+// the other counters unconstrained.
+constexpr int kWaitVmem0 = 0x0F70;
 
 constexpr CoefTable<float> kCoefF = make_coef_table<float>();
 constexpr CoefTable<double> kCoefD = make_coef_table<double>();

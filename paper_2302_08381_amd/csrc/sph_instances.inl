@@ -227,8 +227,14 @@ KernelInfo SPH_CAT(bwd_info_, SPH_SUFFIX)(int L) {
   const int nw = bwd_waves<T>(K);
   const int stride = nw == 2 ? bwd_stride<T, 2>(K) : bwd_stride<T, 1>(K);
   const size_t lds = sizeof(T) * static_cast<size_t>(4 * 16 * nw * stride);  // sized by K: small l_max fit more blocks
-  // double: a resident grid for the pipelined loop over tiles
-  const int bpc = std::is_same_v<T, float> ? 0 : 1;
+  // The pipelined loop over tiles runs on a resident grid, except for float
+  // tiles too wide for four blocks in a CU's 160 KiB of LDS (l_max = 8:
+  // three blocks, 215 us resident against 202 us at one tile per block; at
+  // l_max 4 and 6, where the waves bound residency, the resident grid is
+  // 3-22 % faster, as it is for double at l_max = 8).
+  const bool pipe = nw == 2 ? kBwdPipe<T, 2> : kBwdPipe<T, 1>;
+  const bool lds_bound = std::is_same_v<T, float> && 4 * lds > 160 * 1024;
+  const int bpc = pipe && !lds_bound ? 1 : 0;
   return KernelInfo{tables().bwd[nw - 1], lds, lds, 16 * nw, kWave * nw, bpc};
 }
 
