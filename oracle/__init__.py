@@ -17,8 +17,9 @@ exactly, up to rounding; Sec. II):
 * :mod:`oracle.recurrence` -- the bulk tier: the textbook spherical-coordinate
   route (Eq. recur-p, Condon-Shortley phase) in numpy ``longdouble``, with the
   gradient from textbook pole-free Ferrers identities.  Stable at any l <= 32.
-* :mod:`oracle.derived` -- backward and double-backward contractions and the
-  per-l error metric, built on the two tiers.
+* :mod:`oracle.derived` -- backward and double-backward contractions, the
+  radial expansion over environments (Eq. expansion) and the per-l error
+  metric, built on the two tiers.
 
 Pins (tests marked ``not gpu``) tie both tiers to closed forms, library
 routines (mpmath), invariants (addition theorems, orthonormality, harmonicity,
@@ -35,6 +36,7 @@ from .derived import (  # noqa: F401
     backward,
     double_backward,
     hessian_contract,
+    radial_expansion,
     per_l_errors,
     component_scales,
 )

@@ -55,6 +55,39 @@ def double_backward(xyz, gY, v, l_max: int, normalize: bool):
     return ggY, hessian_contract(H, gY, v)
 
 
+# ------------------------------------------------------ radial expansion
+def radial_expansion(xyz, offsets, R, l_max: int, normalize: bool):
+    """``c[e, n, l^2+l+m] = sum_{j in e} R[j, l, n] Y_l^m(x_j)``, longdouble.
+
+    The expansion of a set of points in radial functions times spherical
+    harmonics (Sec. I, Eq. expansion).  Environment e holds the points
+    ``offsets[e] <= j < offsets[e+1]`` (CSR); ``R[j, l, n]`` is the value of
+    the radial function R_nl at point j, supplied by the caller (the paper
+    leaves the radial basis open).  With ``normalize`` the harmonics are those
+    of the direction (the equation's Y(r_hat)); without, the solid harmonics
+    r^l Y, i.e. R_nl(r) r^l in the equation's terms.  Empty environments give
+    zeros.
+    """
+    P = np.asarray(xyz, dtype=np.float64).reshape(-1, 3)
+    offsets = np.asarray(offsets, dtype=np.int64)
+    R = np.asarray(R).astype(LD)
+    n_env = offsets.size - 1
+    n_max = R.shape[2]
+    K = (l_max + 1) ** 2
+    Y = real_sph(P, l_max, normalize, gradients=False) if P.shape[0] else np.zeros((0, K), LD)
+    Y = np.asarray(Y).astype(LD)
+    lk = _ls(l_max).astype(np.int64)
+    c = np.zeros((n_env, n_max, K), dtype=LD)
+    for e in range(n_env):
+        b, t = int(offsets[e]), int(offsets[e + 1])
+        if t <= b:
+            continue
+        # weights of column k: R[j, l(k), n]
+        W = R[b:t][:, lk, :]                     # [cnt, K, n_max]
+        c[e] = np.einsum("jkn,jk->nk", W, Y[b:t])
+    return c
+
+
 # ------------------------------------------------------------ error metric
 def _ls(l_max):
     return np.array([l for l in range(l_max + 1) for _ in range(2 * l + 1)], dtype=np.float64)

@@ -425,3 +425,69 @@ def test_golden_exact_tier_values(repo_root):
         assert (np.abs(np.asarray(Yb[0] - Yg, float)) / s[0]).max() < 1e-16
         assert (np.abs(np.asarray(Gb[0] - Gg, float)) / g[0]).max() < 1e-16
         assert (np.abs(np.asarray(Hd[0] - Hg, float)) / h[0]).max() < 1e-16
+
+
+# -------------------------------------------------- radial expansion (Eq. expansion)
+def _expansion_case(seed, counts, l_max, n_max):
+    rng = np.random.default_rng(seed)
+    offs = np.zeros(len(counts) + 1, np.int64)
+    np.cumsum(counts, out=offs[1:])
+    pts = rng.standard_normal((int(offs[-1]), 3)) * rng.uniform(0.5, 2.0, (int(offs[-1]), 1))
+    R = rng.standard_normal((int(offs[-1]), l_max + 1, n_max))
+    return pts, offs, R
+
+
+@pytest.mark.parametrize("normalize", [False, True])
+def test_radial_expansion_power_spectrum_addition_theorem(normalize):
+    """sum_m c_nlm c_n'lm = (2l+1)/(4 pi) sum_{j,j'} R_jln R_j'ln' s_j s_j' P_l(cos g_jj')
+    by the addition theorem (s = 1, or r^l for the solid harmonics), with P_l
+    from scipy: pins the sum over the environment, the degree each weight
+    goes with, and the harmonics, independently of the oracle's own route."""
+    from scipy.special import eval_legendre
+    L, NM = 6, 3
+    counts = [5, 0, 1, 9]
+    pts, offs, R = _expansion_case(41, counts, L, NM)
+    c = oracle.radial_expansion(pts, offs, R, L, normalize)
+    assert c.shape == (4, NM, (L + 1) ** 2)
+    assert np.all(c[1] == 0)
+    for e in range(4):
+        b, t = offs[e], offs[e + 1]
+        P = pts[b:t]
+        r = np.sqrt((P * P).sum(1))
+        cosg = np.clip((P / r[:, None]) @ (P / r[:, None]).T, -1.0, 1.0)
+        for l in range(L + 1):
+            cl = np.asarray(c[e][:, l * l:(l + 1) ** 2], float)
+            lhs = cl @ cl.T
+            s = np.ones_like(r) if normalize else r ** l
+            W = R[b:t, l, :] * s[:, None]                       # [cnt, NM]
+            rhs = (2 * l + 1) / (4 * np.pi) * W.T @ eval_legendre(l, cosg) @ W
+            np.testing.assert_allclose(lhs, rhs, rtol=1e-11, atol=1e-12 * (1 + np.abs(rhs).max()))
+
+
+def test_radial_expansion_rotation_invariance_and_single_point():
+    """The power spectrum of an environment is unchanged by a rotation of all
+    its points; a one-point environment with R = 1 is that point's harmonics."""
+    L, NM = 5, 2
+    pts, offs, R = _expansion_case(43, [7], L, NM)
+    q, _ = np.linalg.qr(np.random.default_rng(44).standard_normal((3, 3)))
+    c0 = np.asarray(oracle.radial_expansion(pts, offs, R, L, True), float)[0]
+    c1 = np.asarray(oracle.radial_expansion(pts @ q.T, offs, R, L, True), float)[0]
+    for l in range(L + 1):
+        sl = slice(l * l, (l + 1) ** 2)
+        np.testing.assert_allclose(c0[:, sl] @ c0[:, sl].T, c1[:, sl] @ c1[:, sl].T, rtol=1e-11, atol=1e-13)
+    one = np.array([[0.3, -1.1, 0.7]])
+    c = oracle.radial_expansion(one, np.array([0, 1]), np.ones((1, L + 1, 1)), L, False)
+    Y = oracle.real_sph(one, L, False, gradients=False)
+    assert np.all(c[0, 0] == Y[0])
+
+
+def test_mutation_expansion_degree_of_weight_is_caught(monkeypatch):
+    """Weights taken from the next degree's radial function fail the pin."""
+    from oracle import derived
+    good = derived._ls
+
+    def shifted(l_max):
+        return np.minimum(good(l_max) + 1, l_max)
+    monkeypatch.setattr(derived, "_ls", shifted)
+    with pytest.raises(AssertionError):
+        test_radial_expansion_power_spectrum_addition_theorem(True)
