@@ -304,6 +304,31 @@ def extras(dev):
                         "batched_points_per_s": nb / tbat, "plain_points_per_s": nb / tpl,
                         "config": sph.sph_batched_get_config(Lb, True, torch.float32, True, True)}
     out["batched_20k_envs_f32"] = bat
+    # radial expansion of the same environments: c[e,n,lm] = sum_j R_nl(r_j)
+    # Y_lm(x_j), 8 radial channels (Gaussian basis, cutoff 5), fused against
+    # the harmonics stored by the values-only kernel and contracted by torch
+    from workloads import gaussian_radial_basis
+    env_of = torch.repeat_interleave(torch.arange(offs.size - 1, device=dev), oc[1:] - oc[:-1])
+    exp = {}
+    NMX = 8
+    for Lb in (3, 6, 8, 12):
+        Kb = (Lb + 1) ** 2
+        Rc = torch.as_tensor(gaussian_radial_basis(pts, Lb, NMX, 5.0), dtype=torch.float32).to(dev)
+        cc = torch.empty((offs.size - 1, NMX, Kb), device=dev)
+        tex = _time(lambda: sph.sph_radial_expansion(xc, oc, Rc, Lb, True, out=cc), 20)
+        lk = torch.tensor([l for l in range(Lb + 1) for _ in range(2 * l + 1)], device=dev)
+        Yu = torch.empty((nb, Kb), device=dev)
+        acc = torch.empty((offs.size - 1, Kb, NMX), device=dev)
+
+        def unfused():
+            sph.sph_compute(xc, Lb, True, Y=Yu)
+            acc.zero_()
+            acc.index_add_(0, env_of, Rc[:, lk, :] * Yu[:, :, None])
+        tun = _time(unfused, 5)
+        byts = nb * 4 * (3 + (Lb + 1) * NMX) + (offs.size - 1) * (8 + 4 * NMX * Kb)
+        exp[str(Lb)] = {"fused_s": tex, "unfused_s": tun, "points": nb, "n_max": NMX,
+                        "fused_points_per_s": nb / tex, "fused_GB_per_s": byts / tex / 1e9}
+    out["radial_expansion_20k_envs_f32"] = exp
     return out
 
 

@@ -163,6 +163,37 @@ int32_t sph_batched_compute(const void* xyz, const int64_t* offsets, int64_t n_e
                             void* grad_xyz, int32_t* status, void* stream);
 
 /*
+ * sph_radial_expansion -- the expansion of each environment in radial
+ * functions times harmonics (Sec. I, Eq. expansion):
+ *   c[e, n, l^2+l+m] = sum over offsets[e] <= j < offsets[e+1] of
+ *                      R[j, l, n] * Y_l^m(xyz[j])
+ * with Y the normalised harmonics of the direction (normalize = 1) or the
+ * solid harmonics r^l Y (normalize = 0).  The radial values R are the
+ * caller's: the paper leaves the radial basis open.  The harmonics are
+ * contracted on chip and never written to memory.
+ *   xyz        in  [n_points,3]
+ *   offsets    in  int64 [n_env+1], DEVICE memory (CSR, as in
+ *              sph_batched_compute)
+ *   n_env      number of environments (>= 0)
+ *   n_points   total number of points; must equal offsets[n_env]
+ *   R          in  [n_points, l_max+1, n_max]: R[j,l,n] = R_nl(r_j)
+ *   n_max      radial channels, 1 .. 64
+ *   c          out [n_env, n_max, (l_max+1)^2]; empty environments get 0
+ *   status     out int32 [1], DEVICE memory (may be NULL): SPH_OK or
+ *              SPH_ERR_OFFSETS, checked as in sph_batched_compute.  With
+ *              inconsistent offsets each environment's range is clamped to
+ *              [0, n_points] (no access outside the buffers) and c is
+ *              undefined.
+ * SPH_ERR_INVALID if l_max and n_max need more than one block's 160 KiB of
+ * LDS for an 8-point chunk (never for n_max <= 8, or l_max <= 16 with
+ * n_max <= 32).
+ */
+int32_t sph_radial_expansion(const void* xyz, const int64_t* offsets, int64_t n_env,
+                             int64_t n_points, const void* R, int32_t n_max,
+                             int32_t l_max, int32_t normalize, int32_t dtype,
+                             void* c, int32_t* status, void* stream);
+
+/*
  * sph_batched_set_options -- batched-path controls (process-wide).
  *   use_graph  1: replay cached hipGraphs (default); 0: plain launches
  *   autotune   1: time the candidate launches on first use (default);

@@ -5,7 +5,8 @@ include/sph.h).  This package is its thin Python face:
 
 * :mod:`._native` -- one function per C entry point, same names
   (``sph_compute``, ``sph_compute_with_gradients``, ``sph_backward``,
-  ``sph_double_backward``, ``sph_batched_compute`` ...), torch tensors in,
+  ``sph_double_backward``, ``sph_batched_compute``, ``sph_radial_expansion``
+  ...), torch tensors in,
   raw device pointers and the current HIP stream out;
 * :mod:`.autograd` -- ``spherical_harmonics`` / ``SphericalHarmonics`` with
   first and second derivatives.
@@ -25,6 +26,7 @@ from ._native import (  # noqa: F401
     sph_compute,
     sph_compute_with_gradients,
     sph_double_backward,
+    sph_radial_expansion,
     version,
 )
 from .autograd import (  # noqa: F401

@@ -45,6 +45,7 @@ _SIGNATURES = {
     "sph_backward": (_i32, [_vp, _vp, _i64, _i32, _i32, _vp, _vp]),
     "sph_double_backward": (_i32, [_vp, _vp, _vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp]),
     "sph_batched_compute": (_i32, [_vp, _vp, _i64, _i64, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "sph_radial_expansion": (_i32, [_vp, _vp, _i64, _i64, _vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp]),
     "sph_batched_set_options": (_i32, [_i32, _i32]),
     "sph_batched_get_config": (_i32, [_i32, _i32, _i32, _i32, _i32, ctypes.c_char_p, _i32]),
     "sph_batched_set_config": (_i32, [_i32, _i32, _i32, _i32, _i32, _i32, _i32]),
@@ -247,6 +248,35 @@ def sph_batched_compute(xyz: torch.Tensor, offsets: torch.Tensor, l_max: int, no
                                          _dtype_code(xyz), _ptr(Y), _ptr(dY), _ptr(grad_Y), _ptr(gx),
                                          _ptr(status), _stream(xyz.device)))
     return {"Y": Y, "dY": dY, "grad_xyz": gx, "status": status}
+
+
+def sph_radial_expansion(xyz: torch.Tensor, offsets: torch.Tensor, R: torch.Tensor, l_max: int,
+                         normalize: bool = True, status: torch.Tensor | None = None,
+                         out: torch.Tensor | None = None) -> torch.Tensor:
+    """c[n_env, n_max, K] = sum over each environment's points of R[j,l,n] Y_l^m(x_j)
+    (include/sph.h: sph_radial_expansion).  R is [n_points, l_max+1, n_max]."""
+    _check_xyz(xyz)
+    n = xyz.shape[0]
+    K = (int(l_max) + 1) ** 2
+    if offsets.dtype != torch.int64 or offsets.dim() != 1 or offsets.device != xyz.device \
+            or not offsets.is_contiguous():
+        raise ValueError("offsets must be a contiguous int64 [n_env+1] tensor on the device of xyz")
+    n_env = offsets.shape[0] - 1
+    if n_env < 0:
+        raise ValueError("offsets needs at least one entry")
+    if R.dim() != 3:
+        raise ValueError("R must be [n_points, l_max+1, n_max]")
+    n_max = R.shape[2]
+    _need(R, "R", (n, int(l_max) + 1, n_max), xyz.dtype, xyz.device)
+    c = torch.empty((n_env, n_max, K), dtype=xyz.dtype, device=xyz.device) if out is None else \
+        _need(out, "out", (n_env, n_max, K), xyz.dtype, xyz.device)
+    if status is not None:
+        _need(status, "status", (1,), torch.int32, xyz.device)
+    with torch.cuda.device(xyz.device):
+        _check(lib().sph_radial_expansion(_ptr(xyz), _ptr(offsets), n_env, n, _ptr(R), int(n_max), int(l_max),
+                                          int(bool(normalize)), _dtype_code(xyz), _ptr(c), _ptr(status),
+                                          _stream(xyz.device)))
+    return c
 
 
 def sph_batched_set_options(use_graph: bool = True, autotune: bool = True):

@@ -42,6 +42,8 @@ SOURCES = [
     "sph_kernels_derivs_f64_n1_m1.hip",
     "sph_kernels_derivs_f64_n1_m2.hip",
     "sph_kernels_bwd_f64.hip",
+    "sph_kernels_expand_f32.hip",
+    "sph_kernels_expand_f64.hip",
     "sph_api.cpp",
 ]
 COMMON = [

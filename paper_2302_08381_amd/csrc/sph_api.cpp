@@ -415,6 +415,50 @@ int32_t sph_double_backward(const void* xyz, const void* grad_Y, const void* v, 
   return ok();
 }
 
+int32_t sph_radial_expansion(const void* xyz, const int64_t* offsets, int64_t n_env, int64_t n_points,
+                             const void* R, int32_t n_max, int32_t l_max, int32_t normalize, int32_t dtype,
+                             void* c, int32_t* status, void* stream) {
+  int32_t st = check_common(n_points, l_max, dtype);
+  if (st != SPH_OK) return st;
+  if ((st = check_norm(normalize)) != SPH_OK) return st;
+  if (n_env < 0) return fail(SPH_ERR_INVALID, "n_env must be >= 0");
+  if (n_max < 1 || n_max > 64) return fail(SPH_ERR_INVALID, "n_max must be in [1, 64]");
+  if (offsets == nullptr) return fail(SPH_ERR_NULL, "offsets is required");
+  if (n_env > 0 && c == nullptr) return fail(SPH_ERR_NULL, "c is required");
+  if (n_points > 0 && (xyz == nullptr || R == nullptr)) return fail(SPH_ERR_NULL, "xyz and R are required");
+  if (n_env == 0 && status == nullptr) return ok();
+  const size_t w = elem_size(dtype);
+  const size_t K = static_cast<size_t>(sph_num_components(l_max));
+  const size_t un = static_cast<size_t>(n_points), ue = static_cast<size_t>(n_env);
+  const size_t nr = static_cast<size_t>(l_max + 1) * static_cast<size_t>(n_max);
+  if ((st = check_no_overlap({{c, ue * n_max * K * w, "c"}, {status, status ? size_t(4) : size_t(0), "status"}},
+                             {{xyz, un * 3 * w, "xyz"}, {R, un * nr * w, "R"},
+                              {offsets, (ue + 1) * 8, "offsets"}, {c, ue * n_max * K * w, "c"},
+                              {status, status ? size_t(4) : size_t(0), "status"}})) != SPH_OK)
+    return st;
+  const sph::KernelInfo ki = dtype == SPH_F64 ? sph::expand_info_f64(l_max, normalize)
+                                              : sph::expand_info_f32(l_max, normalize);
+  if (ki.fn == nullptr) return fail(SPH_ERR_INVALID, "no kernel for these arguments");
+  // The largest chunk (points per LDS tile) within 64 KiB, two blocks per
+  // CU; else an 8-point chunk within the 160 KiB of one CU.
+  auto lds_of = [&](int chunk) {
+    return dtype == SPH_F64 ? sph::expand_lds_bytes<double>(l_max, n_max, chunk)
+                            : sph::expand_lds_bytes<float>(l_max, n_max, chunk);
+  };
+  int chunk = 128;
+  while (chunk > 8 && lds_of(chunk) > 64 * 1024) chunk /= 2;
+  const size_t lds = lds_of(chunk);
+  if (lds > 160 * 1024) return fail(SPH_ERR_INVALID, "l_max and n_max need more LDS than one block has");
+  hipError_t e = ensure_lds(ki.fn, lds);
+  if (e != hipSuccess) return device_fail(e, "hipFuncSetAttribute");
+  sph::ExpandParams p{xyz, R, offsets, n_env, n_points, l_max, n_max, chunk, c, status};
+  // one environment per block; a grid-stride loop beyond 2^20 environments
+  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(n_env, int64_t(1) << 20));
+  e = launch(ki.fn, static_cast<unsigned>(grid), ki.block, lds, &p, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_fail(e, "radial expansion launch");
+  return ok();
+}
+
 int32_t sph_batched_set_options(int32_t use_graph, int32_t autotune) {
   if ((use_graph != 0 && use_graph != 1) || (autotune != 0 && autotune != 1))
     return fail(SPH_ERR_INVALID, "options must be 0 or 1");

@@ -44,6 +44,37 @@ struct DbwdParams {
   void* gxyz2; // nullable
 };
 
+// Radial expansion over CSR environments (k_expand).
+struct ExpandParams {
+  const void* xyz;         // [n,3]
+  const void* R;           // [n, L+1, n_max]
+  const int64_t* offsets;  // [n_env+1]
+  int64_t n_env;
+  int64_t n;               // points (offsets[n_env] when consistent)
+  int32_t L;
+  int32_t n_max;
+  int32_t chunk;           // points per LDS chunk (<= 128)
+  void* c;                 // [n_env, n_max, K]
+  int32_t* status;         // device status word or null
+};
+
+// LDS layout of one block (elements of T):
+//   Y tile:   chunk rows of stride expand_ystride(K) (odd: conflict-free
+//             column reads and row writes)
+//   R tile:   chunk rows of (L+1) * NP, NP = n_max rounded up to 4, zero
+//             padded, so each thread's four channels are one aligned vector
+//   C tile:   NP * K partial sums
+__host__ __device__ constexpr int expand_ystride(int K) { return K | 1; }
+__host__ __device__ constexpr int expand_np(int n_max) { return (n_max + 3) & ~3; }
+template <typename T>
+__host__ __device__ constexpr size_t expand_lds_bytes(int L, int n_max, int chunk) {
+  const int K = (L + 1) * (L + 1);
+  // the Y tile is rounded to 16 bytes so the R tile starts aligned
+  const size_t ytile = (static_cast<size_t>(chunk) * expand_ystride(K) * sizeof(T) + 15) & ~size_t(15);
+  return ytile + sizeof(T) * (static_cast<size_t>(chunk) * (L + 1) * expand_np(n_max) +
+                              static_cast<size_t>(expand_np(n_max)) * K);
+}
+
 // A kernel's host stub, its dynamic LDS bytes (for the l_max it was looked
 // up with), and for the forward with derivatives the LDS bytes when the
 // backward is fused (the extra upstream-gradient tile); tile_points is the
@@ -97,5 +128,10 @@ KernelInfo bwd_info_f32(int L);
 KernelInfo bwd_info_f64(int L);
 KernelInfo dbwd_info_f32(int L, int normalize);
 KernelInfo dbwd_info_f64(int L, int normalize);
+// Radial expansion: the kernel of the m-extent bucket of L (run-time degree);
+// lds_bytes is left 0 (it depends on n_max and the chunk, see
+// expand_lds_bytes), block = 128 threads.
+KernelInfo expand_info_f32(int L, int normalize);
+KernelInfo expand_info_f64(int L, int normalize);
 
 }  // namespace sph

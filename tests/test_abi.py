@@ -29,7 +29,7 @@ def lib():
 def test_header_declares_the_documented_entry_points():
     names = header_functions()
     for required in ("sph_compute", "sph_compute_with_gradients", "sph_backward",
-                     "sph_double_backward", "sph_batched_compute"):
+                     "sph_double_backward", "sph_batched_compute", "sph_radial_expansion"):
         assert required in names
 
 
@@ -123,3 +123,22 @@ def test_set_config_validation(lib):
     assert c(8, 1, 0, 0, 0, 1, 0) == 2         # ... nor for the values-only kernel
     assert c(20, 1, 0, 0, 0, 2, 0) == 2        # values only: runtime_degree is the default at l_max = 20
     assert c(20, 1, 0, 1, 1, 3, 0) == 2        # no degree split with the fused backward past l_max = 12
+
+
+def test_radial_expansion_validation(lib):
+    """Every case fails (or finishes) on the host before any device call."""
+    x = lib.sph_radial_expansion
+    #        xyz   offs  n_env n   R     n_max L  norm dt  c     status stream
+    assert x(FAKE, None, 3, 10, FAKE, 8, 4, 1, 0, FAKE, None, None) == 1    # offsets NULL
+    assert x(FAKE, FAKE, -1, 10, FAKE, 8, 4, 1, 0, FAKE, None, None) == 2   # n_env < 0
+    assert x(FAKE, FAKE, 3, 10, FAKE, 0, 4, 1, 0, FAKE, None, None) == 2    # n_max < 1
+    assert x(FAKE, FAKE, 3, 10, FAKE, 65, 4, 1, 0, FAKE, None, None) == 2   # n_max > 64
+    assert x(FAKE, FAKE, 3, 10, FAKE, 8, 33, 1, 0, FAKE, None, None) == 3   # l_max
+    assert x(FAKE, FAKE, 3, 10, FAKE, 8, 4, 2, 0, FAKE, None, None) == 2    # normalize
+    assert x(FAKE, FAKE, 3, 10, FAKE, 8, 4, 1, 5, FAKE, None, None) == 2    # dtype
+    assert x(FAKE, FAKE, 3, 10, FAKE, 8, 4, 1, 0, None, None, None) == 1    # c NULL
+    assert x(FAKE, FAKE, 3, 10, None, 8, 4, 1, 0, FAKE, None, None) == 1    # R NULL
+    assert x(FAKE, FAKE, 0, 10, FAKE, 8, 4, 1, 0, None, None, None) == 0    # no environments, no status
+    # l_max = 32 with 64 double channels: the 8-point chunk needs > 160 KiB of LDS
+    assert x(FAKE, FAKE, 3, 10, FAKE, 64, 32, 1, 1, FAKE, None, None) == 2
+    assert b"LDS" in lib.sph_last_error()

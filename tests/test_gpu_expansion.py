@@ -1,0 +1,159 @@
+"""Radial expansion over CSR environments (sph_radial_expansion): the sum of
+R_nl(r_j) Y_l^m(x_j) over each environment's points (Eq. expansion),
+against the oracle on the same seeded inputs."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from workloads import SEEDS, csr_environments, gaussian_radial_basis, standard_normal
+
+from _gpu_common import TOL, host_points, to_dev
+
+pytestmark = pytest.mark.gpu
+
+EPS = {torch.float32: float(np.finfo(np.float32).eps), torch.float64: float(np.finfo(np.float64).eps)}
+
+# neighbour counts around the 8..128-point chunks the kernel uses
+COUNTS = [0, 1, 2, 7, 8, 9, 63, 64, 65, 127, 128, 129, 200, 257, 0, 31]
+
+
+def _case(counts, l_max, n_max, seed, radial="normal"):
+    counts = np.asarray(counts, np.int64)
+    offs = np.zeros(counts.size + 1, np.int64)
+    np.cumsum(counts, out=offs[1:])
+    rng = np.random.default_rng(seed)
+    n = int(offs[-1])
+    pts = rng.standard_normal((n, 3)) * rng.uniform(0.5, 2.0, (n, 1))
+    if radial == "normal":
+        R = standard_normal((n, l_max + 1, n_max), seed + 1)
+    else:
+        R = gaussian_radial_basis(pts, l_max, n_max, 5.0)
+    return pts, offs, R
+
+
+def _check(c, pts, offs, R, l_max, normalize, dt, label=""):
+    """|c - c_ref| <= (TOL + cnt eps) sum_j |R_jln| s_jk per entry: each term
+    carries the harmonics' scaled error plus one rounding, and a sum of cnt
+    terms adds at most cnt roundings of the sum of magnitudes."""
+    ref = np.asarray(oracle.radial_expansion(pts, offs, R, l_max, normalize), float)
+    got = c.cpu().double().numpy()
+    assert got.shape == ref.shape
+    s, _, _ = oracle.component_scales(pts, l_max, normalize)
+    lk = np.array([l for l in range(l_max + 1) for _ in range(2 * l + 1)])
+    for e in range(offs.size - 1):
+        b, t = offs[e], offs[e + 1]
+        if t == b:
+            assert np.all(got[e] == 0), (label, e)
+            continue
+        scale = np.einsum("jkn,jk->nk", np.abs(R[b:t][:, lk, :]), s[b:t]) + 1e-300
+        tol = TOL[dt] + (t - b) * EPS[dt]
+        err = np.abs(got[e] - ref[e]) / scale
+        assert np.isfinite(got[e]).all() and err.max() <= tol, (label, e, int(t - b), float(err.max()), tol)
+
+
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+@pytest.mark.parametrize("l_max,n_max,normalize", [
+    (0, 1, True), (1, 3, False), (3, 8, True), (6, 5, True), (8, 8, True), (8, 8, False),
+    (12, 4, True), (8, 13, True)])
+def test_expansion_matches_oracle(dt, l_max, n_max, normalize):
+    import paper_2302_08381_amd as sph
+    print(f"expansion {dt} l_max={l_max} n_max={n_max} normalize={normalize}", flush=True)
+    pts, offs, R = _case(COUNTS, l_max, n_max, 300 + 7 * l_max + n_max)
+    xyz = to_dev(pts, dt)
+    Rt = to_dev(R, dt)
+    st = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    c = sph.sph_radial_expansion(xyz, torch.as_tensor(offs, device="cuda"), Rt, l_max, normalize, status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    # the oracle sees the rounded inputs the kernel saw
+    _check(c, host_points(xyz), offs, Rt.cpu().double().numpy(), l_max, normalize, dt,
+           f"{dt} L={l_max} n={n_max}")
+
+
+@pytest.mark.parametrize("l_max,n_max", [(20, 4), (32, 8)])
+def test_expansion_large_degree_small_chunks(l_max, n_max):
+    """Large K: 8- to 32-point chunks, so long environments add many partial
+    sums."""
+    import paper_2302_08381_amd as sph
+    dt = torch.float64
+    print(f"expansion large l_max={l_max} n_max={n_max}", flush=True)
+    pts, offs, R = _case([0, 1, 9, 40, 100], l_max, n_max, 77 + l_max)
+    xyz = to_dev(pts, dt)
+    Rt = to_dev(R, dt)
+    c = sph.sph_radial_expansion(xyz, torch.as_tensor(offs, device="cuda"), Rt, l_max, True)
+    torch.cuda.synchronize()
+    _check(c, host_points(xyz), offs, Rt.cpu().double().numpy(), l_max, True, dt, f"L={l_max}")
+
+
+def test_expansion_workload_environments_against_unfused():
+    """The batched workload's environments (8..128 neighbours in the shell
+    0.5..5), float32, Gaussian radial basis, l_max 3, 6, 8, 12: the fused
+    expansion against the oracle on a sample of environments, and against
+    the unfused composition (harmonics stored, then contracted by torch in
+    float64) on all of them."""
+    import paper_2302_08381_amd as sph
+    pts, offs = csr_environments(2000, 8, 128, 0.5, 5.0, SEEDS["batched"])
+    dt = torch.float32
+    xyz = to_dev(pts, dt)
+    o = torch.as_tensor(offs, device="cuda")
+    env_of = torch.repeat_interleave(torch.arange(offs.size - 1, device="cuda"), o[1:] - o[:-1])
+    for L in (3, 6, 8, 12):
+        print(f"expansion workload l_max={L}", flush=True)
+        R = gaussian_radial_basis(host_points(xyz), L, 8, 5.0)
+        Rt = to_dev(R, dt)
+        c = sph.sph_radial_expansion(xyz, o, Rt, L, True)
+        Y = sph.sph_compute(xyz, L, True).double()
+        lk = torch.tensor([l for l in range(L + 1) for _ in range(2 * l + 1)], device="cuda")
+        W = Rt.double()[:, lk, :]                                    # [N, K, n]
+        ref = torch.zeros((offs.size - 1, (L + 1) ** 2, 8), dtype=torch.float64, device="cuda")
+        ref.index_add_(0, env_of, W * Y[:, :, None])
+        ref = ref.permute(0, 2, 1)
+        # error scale of each sum: sum_j |R_jln| times the size of a degree-l
+        # harmonic, sqrt((2l+1)/4pi) (the scale of the oracle comparisons)
+        sl = torch.sqrt((2 * lk.double() + 1) / (4 * np.pi))
+        mag = torch.zeros_like(ref.permute(0, 2, 1)).index_add_(0, env_of, W.abs() * sl[None, :, None])
+        mag = mag.permute(0, 2, 1)
+        torch.cuda.synchronize()
+        err = ((c.double() - ref).abs() / (mag + 1e-30)).max()
+        assert float(err) <= 2e-5, (L, float(err))  # 1e-5 (harmonics) + 128 roundings of 2^-24
+        sel = np.arange(0, offs.size - 1, 97)
+        sub = np.concatenate([[0], np.cumsum(offs[sel + 1] - offs[sel])])
+        rows = np.concatenate([np.arange(offs[e], offs[e + 1]) for e in sel])
+        _check(c[torch.as_tensor(sel, device="cuda")], host_points(xyz)[rows], sub,
+               Rt.cpu().double().numpy()[rows], L, True, dt, f"workload L={L}")
+
+
+def test_expansion_status_and_degenerate_inputs():
+    import paper_2302_08381_amd as sph
+    dt = torch.float32
+    pts, offs, R = _case([3, 0, 5], 4, 2, 11)
+    xyz = to_dev(pts, dt)
+    Rt = to_dev(R, dt)
+    st = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    # inconsistent offsets: decreasing, wrong start, past the end (clamped, no fault)
+    for bad in (np.array([0, 5, 3, 8]), np.array([1, 2, 3, 8]), np.array([0, 1, 2, 20])):
+        st.fill_(-1)
+        sph.sph_radial_expansion(xyz, torch.as_tensor(bad, device="cuda"), Rt, 4, True, status=st)
+        torch.cuda.synchronize()
+        assert int(st.item()) == 4
+    # no environments: the status is still written
+    st.fill_(-1)
+    e = torch.empty((0, 3), dtype=dt, device="cuda")
+    c = sph.sph_radial_expansion(e, torch.zeros(1, dtype=torch.int64, device="cuda"),
+                                 torch.empty((0, 5, 2), dtype=dt, device="cuda"), 4, True, status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0 and c.shape == (0, 2, 25)
+    # only empty environments: zeros
+    c = sph.sph_radial_expansion(e, torch.zeros(4, dtype=torch.int64, device="cuda"),
+                                 torch.empty((0, 5, 2), dtype=dt, device="cuda"), 4, True)
+    torch.cuda.synchronize()
+    assert c.shape == (3, 2, 25) and bool((c == 0).all())
+    # a point at the origin (normalised: only Y_0^0 survives)
+    z = torch.zeros((1, 3), dtype=dt, device="cuda")
+    c = sph.sph_radial_expansion(z, torch.tensor([0, 1], device="cuda"), torch.ones((1, 5, 1), dtype=dt,
+                                 device="cuda"), 4, True)
+    torch.cuda.synchronize()
+    ref = np.zeros(25)
+    ref[0] = 0.5 / np.sqrt(np.pi)
+    assert np.allclose(c.cpu().numpy()[0, 0], ref, rtol=1e-6, atol=0)

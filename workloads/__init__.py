@@ -108,3 +108,19 @@ def standard_normal(shape, seed: int) -> np.ndarray:
     """iid N(0,1) array of the given shape (upstream gradients and the like)."""
     rng = np.random.default_rng(seed)
     return rng.standard_normal(shape)
+
+
+def gaussian_radial_basis(xyz: np.ndarray, l_max: int, n_max: int, r_cut: float) -> np.ndarray:
+    """Radial values ``R[j, l, n]`` for the expansion of environments: Gaussians
+    of width r_cut/n_max centred on n_max evenly spaced radii in [0, r_cut],
+    times a cosine cutoff that vanishes at r_cut, damped by 1/(1+l) so that
+    every degree gets its own function.  An input of the expansion (the
+    paper leaves the radial basis open), float64 [N, l_max+1, n_max]."""
+    P = np.asarray(xyz, dtype=np.float64).reshape(-1, 3)
+    r = np.sqrt((P * P).sum(1))
+    mu = np.linspace(0.0, r_cut, n_max)
+    w = r_cut / n_max
+    g = np.exp(-((r[:, None] - mu[None, :]) / w) ** 2)                  # [N, n]
+    fc = np.where(r < r_cut, 0.5 * (np.cos(np.pi * r / r_cut) + 1.0), 0.0)
+    damp = 1.0 / (1.0 + np.arange(l_max + 1))
+    return (g * fc[:, None])[:, None, :] * damp[None, :, None]
