@@ -452,8 +452,9 @@ int32_t sph_radial_expansion(const void* xyz, const int64_t* offsets, int64_t n_
   hipError_t e = ensure_lds(ki.fn, lds);
   if (e != hipSuccess) return device_fail(e, "hipFuncSetAttribute");
   sph::ExpandParams p{xyz, R, offsets, n_env, n_points, l_max, n_max, chunk, c, status};
-  // one environment per block; a grid-stride loop beyond 2^20 environments
-  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(n_env, int64_t(1) << 20));
+  // a resident grid: each block walks its environments as a pipeline
+  const int64_t resident = static_cast<int64_t>(num_cus()) * resident_per_cu(ki.fn, ki.block, lds);
+  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(n_env, std::max<int64_t>(resident, 1)));
   e = launch(ki.fn, static_cast<unsigned>(grid), ki.block, lds, &p, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return device_fail(e, "radial expansion launch");
   return ok();

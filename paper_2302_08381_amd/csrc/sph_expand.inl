@@ -17,7 +17,10 @@ namespace sph {
 
 constexpr int kExpandThreads = 128;  // two waves
 constexpr int kExpandAcc = 4;        // radial channels per accumulator item
-constexpr int kExpandRBatch = 32;    // radial values in flight per thread
+// radial values in flight per thread (one batch covers a 64-point chunk of
+// l_max = 8 with 8 channels in float, a 32-point one in double)
+template <typename T>
+inline constexpr int kExpandRBatch = std::is_same_v<T, float> ? 40 : 24;
 
 // Environment e's point range, clamped into [0, n] so that inconsistent
 // offsets (reported through the status word) never index out of bounds.
@@ -29,11 +32,30 @@ __device__ __forceinline__ void env_range(const int64_t* o, int64_t e, int64_t n
   t = hi;
 }
 
-template <typename T, int MM, bool NORM>
+// Values of degrees [la, lb) of one point into its LDS row.  LT >= 0: the
+// degree loop is unrolled to LT with compile-time degrees (each row's
+// coefficients fold to literals), every row behind a uniform range check;
+// LT < 0: the run-time-degree rows of the m-extent bucket MM.
+template <typename T, int MM, int LT, bool NORM>
+__device__ __forceinline__ void expand_rows(const Point<T>& pt, int la, int lb, T* row) {
+  if constexpr (LT >= 0) {
+    T cur[LT + 3], unused[LT + 3];
+#pragma unroll
+    for (int l = 0; l <= LT; ++l) {
+      if (l < la || l >= lb) continue;
+      q_row<T, LT>(l, pt.ez, pt.rxy2, cur);
+      emit_row<T, LT, 0, NORM>(l, unused, cur, pt.ex, pt.ey, pt.ez, pt.inv_r, [&](int k, T v) { row[k] = v; });
+    }
+  } else {
+    emit_values<T, MM, NORM, false>(pt, la, lb, row);
+  }
+}
+
+template <typename T, int MM, int LT, bool NORM>
 __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandParams P) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
-  const int L = P.L;
+  const int L = LT >= 0 ? LT : P.L;
   const int K = (L + 1) * (L + 1);
   const int SY = expand_ystride(K);
   const int NM = P.n_max;
@@ -57,97 +79,144 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandParams P) {
     if (tid == 0) P.status[0] = all_ok ? 0 : 4 /* SPH_ERR_OFFSETS */;
   }
 
-  for (int64_t e = blockIdx.x; e < P.n_env; e += gridDim.x) {
-    int64_t b, t;
-    env_range(P.offsets, e, P.n, b, t);
-    T* ce = c + e * NM * K;
-    for (int64_t j0 = b; j0 < t; j0 += JC) {
-      const int cnt = static_cast<int>(t - j0 < JC ? t - j0 : JC);
-      // The chunk's radial values (global rows [j][l][n], contiguous): the
-      // first batch of loads is issued before the harmonics are computed so
-      // that its latency hides behind them.  Indices past the chunk load its
-      // last element again (in bounds, never stored), which keeps the loads
-      // unconditional.
-      const int nrv = cnt * (L + 1) * NM;
-      const T* Rg = R + j0 * (L + 1) * NM;
-      T rb[kExpandRBatch];
-      auto rload = [&](int base) {
-#pragma unroll
-        for (int u = 0; u < kExpandRBatch; ++u) {
-          const int i = base + tid + u * kExpandThreads;
-          rb[u] = Rg[i < nrv ? i : nrv - 1];
-        }
-      };
-      auto rstore = [&](int base) {
-        __builtin_amdgcn_s_waitcnt(kWaitVmem0);  // one wait for the whole batch
-#pragma unroll
-        for (int u = 0; u < kExpandRBatch; ++u) {
-          const int i = base + tid + u * kExpandThreads;
-          if (i < nrv) {
-            const int row = NP == NM ? 0 : i / NM;
-            sR[NP == NM ? i : row * NP + (i - row * NM)] = rb[u];
-          }
-        }
-      };
-      rload(0);
-      // the chunk's harmonics, one thread per point
-      if (tid < cnt) {
-        const T* q = xyz + (j0 + tid) * 3;
-        const Point<T> pt = make_point<T, NORM>(q[0], q[1], q[2]);
-        emit_values<T, MM, NORM, false>(pt, 0, L + 1, sY + tid * SY);
-      }
-      rstore(0);
-      for (int base = kExpandRBatch * kExpandThreads; base < nrv; base += kExpandRBatch * kExpandThreads) {
-        rload(base);
-        rstore(base);
-      }
-      if (NP != NM) {
-        const int nr = cnt * (L + 1);
-        const int pad = NP - NM;
-        for (int i = tid; i < nr * pad; i += kExpandThreads) {
-          const int row = i / pad;
-          sR[row * NP + NM + (i - row * pad)] = T(0);
-        }
-      }
-      __syncthreads();
-      for (int it = tid; it < items; it += kExpandThreads) {
-        const int g = it / K;
-        const int k = it - g * K;
-        int l = static_cast<int>(sqrtf(static_cast<float>(k)));
-        l += (l + 1) * (l + 1) <= k ? 1 : 0;
-        l -= l * l > k ? 1 : 0;
-        T a[kExpandAcc];
-#pragma unroll
-        for (int u = 0; u < kExpandAcc; ++u) a[u] = j0 == b ? T(0) : sC[(g * kExpandAcc + u) * K + k];
-        using V = typename Vec16<T>::type;
-        constexpr int W = Vec16<T>::n;
-        const T* yc = sY + k;
-        const T* rc = sR + l * NP + g * kExpandAcc;  // 16-byte aligned
-#pragma unroll 4
-        for (int j = 0; j < cnt; ++j) {
-          const T y = yc[j * SY];
-          const V* r = reinterpret_cast<const V*>(rc + j * RS);
-#pragma unroll
-          for (int h = 0; h < kExpandAcc / W; ++h) {
-            const V rv = r[h];
-#pragma unroll
-            for (int u = 0; u < W; ++u) a[h * W + u] += rv[u] * y;
-          }
-        }
-        if (j0 + JC >= t) {
-#pragma unroll
-          for (int u = 0; u < kExpandAcc; ++u)
-            if (g * kExpandAcc + u < NM) ce[(g * kExpandAcc + u) * K + k] = a[u];
-        } else {
-#pragma unroll
-          for (int u = 0; u < kExpandAcc; ++u) sC[(g * kExpandAcc + u) * K + k] = a[u];
-        }
-      }
-      __syncthreads();
+  // The block walks its chunks (environment e = blockIdx.x, + gridDim.x,
+  // ...; points j0 .. j0 + JC of each) as a pipeline: the coordinates and
+  // the first radial batch of chunk i + 1 are loaded into registers while
+  // chunk i's harmonics are computed and contracted.  Indices past a chunk
+  // load its last element again (in bounds, never stored), which keeps the
+  // loads unconditional.  Empty environments get their zeros as the walk
+  // passes them.
+  constexpr int RB = kExpandRBatch<T>;
+  int64_t e = blockIdx.x, b = 0, t = 0, j0 = 0;
+  // moves (e, b, t, j0) to the next chunk at or after environment e (j0 =
+  // start of e when fresh); false when the block has no chunk left
+  auto seek = [&](bool fresh) {
+    if (!fresh) {
+      j0 += JC;
+      if (j0 < t) return true;
+      e += gridDim.x;
     }
-    if (t == b) {  // empty environment
+    for (; e < P.n_env; e += gridDim.x) {
+      env_range(P.offsets, e, P.n, b, t);
+      j0 = b;
+      if (t > b) return true;
+      T* ce = c + e * NM * K;
       for (int i = tid; i < NM * K; i += kExpandThreads) ce[i] = T(0);
     }
+    return false;
+  };
+  T px = T(0), py = T(0), pz = T(0);
+  T rb[RB];
+  auto issue = [&]() {  // coordinates and first radial batch of chunk (e, j0)
+    const int cnt = static_cast<int>(t - j0 < JC ? t - j0 : JC);
+    const int64_t jp = j0 + (tid % JC < cnt ? tid % JC : cnt - 1);
+    px = xyz[jp * 3 + 0];
+    py = xyz[jp * 3 + 1];
+    pz = xyz[jp * 3 + 2];
+    const int nrv = cnt * (L + 1) * NM;
+    const T* Rg = R + j0 * (L + 1) * NM;
+#pragma unroll
+    for (int u = 0; u < RB; ++u) {
+      const int i = tid + u * kExpandThreads;
+      rb[u] = Rg[i < nrv ? i : nrv - 1];
+    }
+  };
+  auto rstore = [&](int base, int nrv) {
+#pragma unroll
+    for (int u = 0; u < RB; ++u) {
+      const int i = base + tid + u * kExpandThreads;
+      if (i < nrv) {
+        const int row = NP == NM ? 0 : i / NM;
+        sR[NP == NM ? i : row * NP + (i - row * NM)] = rb[u];
+      }
+    }
+  };
+
+  bool more = seek(true);
+  if (more) issue();
+  while (more) {
+    const int cnt = static_cast<int>(t - j0 < JC ? t - j0 : JC);
+    const int nrv = cnt * (L + 1) * NM;
+    const int64_t cb = b, ct = t, c0 = j0;
+    T* ce = c + e * NM * K;
+    // this chunk's loads: one wait for all of them
+    __builtin_amdgcn_s_waitcnt(kWaitVmem0);
+    rstore(0, nrv);
+    const T x = px, y = py, z = pz;
+    // radial values past the first batch (chunks of more than RB * 128)
+    for (int base = RB * kExpandThreads; base < nrv; base += RB * kExpandThreads) {
+      const T* Rg = R + c0 * (L + 1) * NM;
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        const int i = base + tid + u * kExpandThreads;
+        rb[u] = Rg[i < nrv ? i : nrv - 1];
+      }
+      __builtin_amdgcn_s_waitcnt(kWaitVmem0);
+      rstore(base, nrv);
+    }
+    if (NP != NM) {
+      const int nr = cnt * (L + 1);
+      const int pad = NP - NM;
+      for (int i = tid; i < nr * pad; i += kExpandThreads) {
+        const int row = i / pad;
+        sR[row * NP + NM + (i - row * pad)] = T(0);
+      }
+    }
+    // the next chunk's loads fly during this chunk's arithmetic
+    more = seek(false);
+    if (more) issue();
+    // The chunk's harmonics: point tid % JC, degrees [la, lb) of part
+    // tid / JC.  A chunk narrower than the block splits each point's degrees
+    // into 128 / JC parts of equal row counts (each row starts its own
+    // recursion, so any part can start at any degree), keeping every thread
+    // busy.
+    if (tid % JC < cnt) {
+      const int parts = kExpandThreads / JC;
+      const int part = tid / JC;
+      const int per = (L + 1 + parts - 1) / parts;
+      const int la = part * per;
+      const int lb = la + per < L + 1 ? la + per : L + 1;
+      if (la < lb) {
+        const Point<T> pt = make_point<T, NORM>(x, y, z);
+        expand_rows<T, MM, LT, NORM>(pt, la, lb, sY + (tid % JC) * SY);
+      }
+    }
+    __syncthreads();
+    const bool last = c0 + JC >= ct;
+    for (int it = tid; it < items; it += kExpandThreads) {
+      const int g = it / K;
+      const int k = it - g * K;
+      int l = static_cast<int>(sqrtf(static_cast<float>(k)));
+      l += (l + 1) * (l + 1) <= k ? 1 : 0;
+      l -= l * l > k ? 1 : 0;
+      T a[kExpandAcc];
+#pragma unroll
+      for (int u = 0; u < kExpandAcc; ++u) a[u] = c0 == cb ? T(0) : sC[(g * kExpandAcc + u) * K + k];
+      using V = typename Vec16<T>::type;
+      constexpr int W = Vec16<T>::n;
+      const T* yc = sY + k;
+      const T* rc = sR + l * NP + g * kExpandAcc;  // 16-byte aligned
+#pragma unroll 4
+      for (int j = 0; j < cnt; ++j) {
+        const T yv = yc[j * SY];
+        const V* r = reinterpret_cast<const V*>(rc + j * RS);
+#pragma unroll
+        for (int h = 0; h < kExpandAcc / W; ++h) {
+          const V rv = r[h];
+#pragma unroll
+          for (int u = 0; u < W; ++u) a[h * W + u] += rv[u] * yv;
+        }
+      }
+      if (last) {
+#pragma unroll
+        for (int u = 0; u < kExpandAcc; ++u)
+          if (g * kExpandAcc + u < NM) ce[(g * kExpandAcc + u) * K + k] = a[u];
+      } else {
+#pragma unroll
+        for (int u = 0; u < kExpandAcc; ++u) sC[(g * kExpandAcc + u) * K + k] = a[u];
+      }
+    }
+    __syncthreads();
   }
 }
 
