@@ -77,6 +77,7 @@ PROFILE_COMMANDS = {
              "python3 {repo}/bench.py --profile --steps 3 --warmup 1",
 }
 KERNEL_ROLES = {"forward": "k_fwd4<", "backward": "k_bwd<"}
+PROFILE_STEPS = 20  # the --steps of the kernel-trace command above
 REFERENCE_COPY = "copyBuffer"  # torch's device-to-device copy of the profile run
 REFERENCE_COPY_BYTES = 1 << 30
 
@@ -123,6 +124,18 @@ def summarize(outdir: str) -> None:
         lines.append(f"| `{name}` | {r['Calls']} | {mean * 1e6:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
                      f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} | {gbs} |")
     lines += ["", f"Algorithmic bytes per launch of either kernel: N * 4 * (3 + 4K) = {alg} (K = {K})."]
+    # the timed region only: the last PROFILE_STEPS launches of each kernel
+    # (the statistics above include the warm-up launches)
+    with open(os.path.join(outdir, "prof_trace", "run_kernel_trace.csv")) as f:
+        trace = list(csv.DictReader(f))
+    lines += ["", f"Timed region (the last {PROFILE_STEPS} launches of each kernel, as bench.py times them):", "",
+              "| kernel | launches | mean us | algorithmic GB/s |", "|---|---|---|---|"]
+    for role, tag in KERNEL_ROLES.items():
+        ds = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in trace if tag in r["Kernel_Name"])
+        ds = ds[-PROFILE_STEPS:]
+        if ds:
+            m = sum(e - b for b, e in ds) / len(ds) * 1e-9
+            lines.append(f"| {role} | {len(ds)} | {m * 1e6:.1f} | {alg / m / 1e9:.0f} |")
     with open(os.path.join(prof, "kernels_l8_f32.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
 

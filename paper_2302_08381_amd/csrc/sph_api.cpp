@@ -436,8 +436,8 @@ int32_t sph_radial_expansion(const void* xyz, const int64_t* offsets, int64_t n_
                               {offsets, (ue + 1) * 8, "offsets"}, {c, ue * n_max * K * w, "c"},
                               {status, status ? size_t(4) : size_t(0), "status"}})) != SPH_OK)
     return st;
-  const sph::KernelInfo ki = dtype == SPH_F64 ? sph::expand_info_f64(l_max, normalize)
-                                              : sph::expand_info_f32(l_max, normalize);
+  const sph::KernelInfo ki = dtype == SPH_F64 ? sph::expand_info_f64(l_max, normalize, n_max)
+                                              : sph::expand_info_f32(l_max, normalize, n_max);
   if (ki.fn == nullptr) return fail(SPH_ERR_INVALID, "no kernel for these arguments");
   // The largest chunk (points per LDS tile) within 64 KiB, two blocks per
   // CU; else an 8-point chunk within the 160 KiB of one CU.

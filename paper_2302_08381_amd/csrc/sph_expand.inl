@@ -16,7 +16,6 @@
 namespace sph {
 
 constexpr int kExpandThreads = 128;  // two waves
-constexpr int kExpandAcc = 4;        // radial channels per accumulator item
 // radial values in flight per thread (one batch covers a 64-point chunk of
 // l_max = 8 with 8 channels in float, a 32-point one in double)
 template <typename T>
@@ -51,7 +50,8 @@ __device__ __forceinline__ void expand_rows(const Point<T>& pt, int la, int lb, 
   }
 }
 
-template <typename T, int MM, int LT, bool NORM>
+// ACC: radial channels per accumulator item (4 or 8; see expand_acc).
+template <typename T, int MM, int LT, bool NORM, int ACC>
 __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandParams P) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
@@ -59,7 +59,7 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandParams P) {
   const int K = (L + 1) * (L + 1);
   const int SY = expand_ystride(K);
   const int NM = P.n_max;
-  const int NP = expand_np(NM);
+  const int NP = expand_np(NM, ACC);
   const int RS = (L + 1) * NP;  // R tile row stride
   const int JC = P.chunk;
   T* sY = reinterpret_cast<T*>(smem);
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandParams P) {
   const T* xyz = static_cast<const T*>(P.xyz);
   const T* R = static_cast<const T*>(P.R);
   T* c = static_cast<T*>(P.c);
-  const int items = K * (NP / kExpandAcc);
+  const int items = K * (NP / ACC);
 
   // CSR consistency, by the first wave of block 0 (one writer, no atomics)
   if (P.status != nullptr && blockIdx.x == 0 && tid < kWave) {
@@ -189,19 +189,19 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandParams P) {
       int l = static_cast<int>(sqrtf(static_cast<float>(k)));
       l += (l + 1) * (l + 1) <= k ? 1 : 0;
       l -= l * l > k ? 1 : 0;
-      T a[kExpandAcc];
+      T a[ACC];
 #pragma unroll
-      for (int u = 0; u < kExpandAcc; ++u) a[u] = c0 == cb ? T(0) : sC[(g * kExpandAcc + u) * K + k];
+      for (int u = 0; u < ACC; ++u) a[u] = c0 == cb ? T(0) : sC[(g * ACC + u) * K + k];
       using V = typename Vec16<T>::type;
       constexpr int W = Vec16<T>::n;
       const T* yc = sY + k;
-      const T* rc = sR + l * NP + g * kExpandAcc;  // 16-byte aligned
+      const T* rc = sR + l * NP + g * ACC;  // 16-byte aligned (NP, ACC multiples of 4)
 #pragma unroll 4
       for (int j = 0; j < cnt; ++j) {
         const T yv = yc[j * SY];
         const V* r = reinterpret_cast<const V*>(rc + j * RS);
 #pragma unroll
-        for (int h = 0; h < kExpandAcc / W; ++h) {
+        for (int h = 0; h < ACC / W; ++h) {
           const V rv = r[h];
 #pragma unroll
           for (int u = 0; u < W; ++u) a[h * W + u] += rv[u] * yv;
@@ -209,11 +209,11 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandParams P) {
       }
       if (last) {
 #pragma unroll
-        for (int u = 0; u < kExpandAcc; ++u)
-          if (g * kExpandAcc + u < NM) ce[(g * kExpandAcc + u) * K + k] = a[u];
+        for (int u = 0; u < ACC; ++u)
+          if (g * ACC + u < NM) ce[(g * ACC + u) * K + k] = a[u];
       } else {
 #pragma unroll
-        for (int u = 0; u < kExpandAcc; ++u) sC[(g * kExpandAcc + u) * K + k] = a[u];
+        for (int u = 0; u < ACC; ++u) sC[(g * ACC + u) * K + k] = a[u];
       }
     }
     __syncthreads();

@@ -12,35 +12,40 @@ using T = float;
 // the m-extent bucket.
 constexpr int kSpecMax = 12;
 
-template <bool NORM, int... Is>
+template <bool NORM, int ACC, int... Is>
 void fill_expand(const void** out, std::integer_sequence<int, Is...>) {
-  const void* tbl[] = {reinterpret_cast<const void*>(&k_expand<T, kBuckets[Is], -1, NORM>)...};
+  const void* tbl[] = {reinterpret_cast<const void*>(&k_expand<T, kBuckets[Is], -1, NORM, ACC>)...};
   for (size_t i = 0; i < sizeof...(Is); ++i) out[i] = tbl[i];
 }
 
-template <bool NORM, int... Ls>
+template <bool NORM, int ACC, int... Ls>
 void fill_spec(const void** out, std::integer_sequence<int, Ls...>) {
-  const void* tbl[] = {reinterpret_cast<const void*>(&k_expand<T, Ls, Ls, NORM>)...};
+  const void* tbl[] = {reinterpret_cast<const void*>(&k_expand<T, Ls, Ls, NORM, ACC>)...};
   for (size_t i = 0; i < sizeof...(Ls); ++i) out[i] = tbl[i];
 }
 
 struct Tables {
-  const void* fn[2][kNumBuckets];
-  const void* spec[2][kSpecMax + 1];
+  const void* fn[2][2][kNumBuckets];  // [normalize][ACC == 8]
+  const void* spec[2][2][kSpecMax + 1];
   Tables() {
-    fill_expand<false>(fn[0], std::make_integer_sequence<int, kNumBuckets>{});
-    fill_expand<true>(fn[1], std::make_integer_sequence<int, kNumBuckets>{});
-    fill_spec<false>(spec[0], std::make_integer_sequence<int, kSpecMax + 1>{});
-    fill_spec<true>(spec[1], std::make_integer_sequence<int, kSpecMax + 1>{});
+    fill_expand<false, 4>(fn[0][0], std::make_integer_sequence<int, kNumBuckets>{});
+    fill_expand<true, 4>(fn[1][0], std::make_integer_sequence<int, kNumBuckets>{});
+    fill_expand<false, 8>(fn[0][1], std::make_integer_sequence<int, kNumBuckets>{});
+    fill_expand<true, 8>(fn[1][1], std::make_integer_sequence<int, kNumBuckets>{});
+    fill_spec<false, 4>(spec[0][0], std::make_integer_sequence<int, kSpecMax + 1>{});
+    fill_spec<true, 4>(spec[1][0], std::make_integer_sequence<int, kSpecMax + 1>{});
+    fill_spec<false, 8>(spec[0][1], std::make_integer_sequence<int, kSpecMax + 1>{});
+    fill_spec<true, 8>(spec[1][1], std::make_integer_sequence<int, kSpecMax + 1>{});
   }
 };
 
 }  // namespace
 
-KernelInfo expand_info_f32(int L, int normalize) {
+KernelInfo expand_info_f32(int L, int normalize, int n_max) {
   static const Tables t;
-  if (L < 0 || L > kMaxLmax || (normalize != 0 && normalize != 1)) return KernelInfo{nullptr, 0, 0, 0, 0};
-  const void* fn = L <= kSpecMax ? t.spec[normalize][L] : t.fn[normalize][bucket_index(L)];
+  if (L < 0 || L > kMaxLmax || (normalize != 0 && normalize != 1) || n_max < 1) return KernelInfo{nullptr, 0, 0, 0, 0};
+  const int a = expand_acc(L, n_max) == 8 ? 1 : 0;
+  const void* fn = L <= kSpecMax ? t.spec[normalize][a][L] : t.fn[normalize][a][bucket_index(L)];
   return KernelInfo{fn, 0, 0, 0, kExpandThreads};
 }
 

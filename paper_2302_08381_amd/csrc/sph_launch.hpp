@@ -61,18 +61,26 @@ struct ExpandParams {
 // LDS layout of one block (elements of T):
 //   Y tile:   chunk rows of stride expand_ystride(K) (odd: conflict-free
 //             column reads and row writes)
-//   R tile:   chunk rows of (L+1) * NP, NP = n_max rounded up to 4, zero
-//             padded, so each thread's four channels are one aligned vector
+//   R tile:   chunk rows of (L+1) * NP, NP = n_max rounded up to the
+//             accumulator width (4 or 8), zero padded, so each thread's
+//             channels are aligned 16-byte vectors
 //   C tile:   NP * K partial sums
 __host__ __device__ constexpr int expand_ystride(int K) { return K | 1; }
-__host__ __device__ constexpr int expand_np(int n_max) { return (n_max + 3) & ~3; }
+__host__ __device__ constexpr int expand_np(int n_max, int acc) { return (n_max + acc - 1) / acc * acc; }
+// Channels per accumulator item: 8 where 4 would need more than one pass of
+// the block's 128 threads over the (column, channel group) items and there
+// are more than 4 channels; else 4.  (Measured on 20 000 environments with 8
+// channels: 8 is faster at l_max 8 and 12, 4 at l_max 3 and 6.)
+__host__ __device__ constexpr int expand_acc(int L, int n_max) {
+  return n_max > 4 && (L + 1) * (L + 1) * expand_np(n_max, 4) / 4 > 128 ? 8 : 4;
+}
 template <typename T>
 __host__ __device__ constexpr size_t expand_lds_bytes(int L, int n_max, int chunk) {
   const int K = (L + 1) * (L + 1);
   // the Y tile is rounded to 16 bytes so the R tile starts aligned
   const size_t ytile = (static_cast<size_t>(chunk) * expand_ystride(K) * sizeof(T) + 15) & ~size_t(15);
-  return ytile + sizeof(T) * (static_cast<size_t>(chunk) * (L + 1) * expand_np(n_max) +
-                              static_cast<size_t>(expand_np(n_max)) * K);
+  const int np = expand_np(n_max, expand_acc(L, n_max));
+  return ytile + sizeof(T) * (static_cast<size_t>(chunk) * (L + 1) * np + static_cast<size_t>(np) * K);
 }
 
 // A kernel's host stub, its dynamic LDS bytes (for the l_max it was looked
@@ -128,10 +136,12 @@ KernelInfo bwd_info_f32(int L);
 KernelInfo bwd_info_f64(int L);
 KernelInfo dbwd_info_f32(int L, int normalize);
 KernelInfo dbwd_info_f64(int L, int normalize);
-// Radial expansion: the kernel of the m-extent bucket of L (run-time degree);
+// Radial expansion: the compile-time kernel of L (float L <= 12, double
+// L <= 8), else the one of the m-extent bucket of L (run-time degree), with
+// the accumulator width expand_acc(L, n_max);
 // lds_bytes is left 0 (it depends on n_max and the chunk, see
 // expand_lds_bytes), block = 128 threads.
-KernelInfo expand_info_f32(int L, int normalize);
-KernelInfo expand_info_f64(int L, int normalize);
+KernelInfo expand_info_f32(int L, int normalize, int n_max);
+KernelInfo expand_info_f64(int L, int normalize, int n_max);
 
 }  // namespace sph
