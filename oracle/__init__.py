@@ -37,6 +37,7 @@ from .derived import (  # noqa: F401
     double_backward,
     hessian_contract,
     radial_expansion,
+    radial_expansion_backward,
     per_l_errors,
     component_scales,
 )

@@ -88,6 +88,41 @@ def radial_expansion(xyz, offsets, R, l_max: int, normalize: bool):
     return c
 
 
+def radial_expansion_backward(xyz, offsets, R, G, l_max: int, normalize: bool):
+    """Backward of :func:`radial_expansion` for an upstream gradient
+    ``G[e, n, k]`` of c, in longdouble (chain rule):
+
+    * ``grad_R[j, l, n] = sum_m G[e, n, l^2+l+m] Y_l^m(x_j)``
+    * ``grad_xyz[j, a] = sum_k gY[j, k] dY_k/dx_a(x_j)`` with
+      ``gY[j, k] = sum_n G[e, n, k] R[j, l(k), n]``
+
+    for the environment e that holds point j.
+    """
+    P = np.asarray(xyz, dtype=np.float64).reshape(-1, 3)
+    offsets = np.asarray(offsets, dtype=np.int64)
+    R = np.asarray(R).astype(LD)
+    G = np.asarray(G).astype(LD)
+    N = P.shape[0]
+    K = (l_max + 1) ** 2
+    gR = np.zeros(R.shape, dtype=LD)
+    gx = np.zeros((N, 3), dtype=LD)
+    if N == 0:
+        return gx, gR
+    Y, dY = real_sph(P, l_max, normalize, gradients=True)
+    lk = _ls(l_max).astype(np.int64)
+    for e in range(offsets.size - 1):
+        b, t = int(offsets[e]), int(offsets[e + 1])
+        if t <= b:
+            continue
+        Ge = G[e]                                           # [n_max, K]
+        gY = np.einsum("nk,jkn->jk", Ge, R[b:t][:, lk, :])  # [cnt, K]
+        gx[b:t] = np.einsum("jk,jak->ja", gY, dY[b:t])
+        prod = np.einsum("nk,jk->jkn", Ge, Y[b:t])           # [cnt, K, n_max]
+        for l in range(l_max + 1):
+            gR[b:t, l, :] = prod[:, l * l:(l + 1) ** 2, :].sum(1)
+    return gx, gR
+
+
 # ------------------------------------------------------------ error metric
 def _ls(l_max):
     return np.array([l for l in range(l_max + 1) for _ in range(2 * l + 1)], dtype=np.float64)

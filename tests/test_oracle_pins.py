@@ -491,3 +491,27 @@ def test_mutation_expansion_degree_of_weight_is_caught(monkeypatch):
     monkeypatch.setattr(derived, "_ls", shifted)
     with pytest.raises(AssertionError):
         test_radial_expansion_power_spectrum_addition_theorem(True)
+
+
+@pytest.mark.parametrize("normalize", [False, True])
+def test_radial_expansion_backward_by_differences(normalize):
+    """grad_xyz against central differences of the oracle's expansion, and
+    grad_R against the expansion's linearity in R: <grad_R, dR> equals
+    <G, c(dR)> exactly."""
+    L, NM = 4, 3
+    pts, offs, R = _expansion_case(47, [4, 0, 6], L, NM)
+    G = np.random.default_rng(48).standard_normal((3, NM, (L + 1) ** 2))
+    gx, gR = oracle.radial_expansion_backward(pts, offs, R, G, L, normalize)
+    h = 1e-5
+    for j in range(pts.shape[0]):
+        for a in range(3):
+            d = np.zeros_like(pts)
+            d[j, a] = h
+            cp = oracle.radial_expansion(pts + d, offs, R, L, normalize)
+            cm = oracle.radial_expansion(pts - d, offs, R, L, normalize)
+            fd = float(((cp - cm) * G).sum()) / (2 * h)
+            assert abs(float(gx[j, a]) - fd) <= 1e-7 * (1 + abs(fd)), (j, a, float(gx[j, a]), fd)
+    dR = np.random.default_rng(49).standard_normal(R.shape)
+    lhs = float((gR * dR).sum())
+    rhs = float((oracle.radial_expansion(pts, offs, dR, L, normalize) * G).sum())
+    assert abs(lhs - rhs) <= 1e-13 * (1 + abs(rhs))
