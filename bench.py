@@ -339,8 +339,11 @@ def extras(dev):
             acc.index_add_(0, env_of, Rc[:, lk, :] * Yu[:, :, None])
         tun = _time(unfused, 5)
         byts = nb * 4 * (3 + (Lb + 1) * NMX) + (offs.size - 1) * (8 + 4 * NMX * Kb)
-        exp[str(Lb)] = {"fused_s": tex, "unfused_s": tun, "points": nb, "n_max": NMX,
-                        "fused_points_per_s": nb / tex, "fused_GB_per_s": byts / tex / 1e9}
+        Gc = torch.as_tensor(standard_normal((offs.size - 1, NMX, Kb), 700 + Lb), dtype=torch.float32).to(dev)
+        tbw = _time(lambda: sph.sph_radial_expansion_backward(xc, oc, Rc, Gc, Lb, True), 10)
+        exp[str(Lb)] = {"fused_s": tex, "unfused_s": tun, "backward_s": tbw, "points": nb, "n_max": NMX,
+                        "fused_points_per_s": nb / tex, "fused_GB_per_s": byts / tex / 1e9,
+                        "backward_points_per_s": nb / tbw}
     out["radial_expansion_20k_envs_f32"] = exp
     return out
 

@@ -194,6 +194,31 @@ int32_t sph_radial_expansion(const void* xyz, const int64_t* offsets, int64_t n_
                              void* c, int32_t* status, void* stream);
 
 /*
+ * sph_radial_expansion_backward -- the backward of sph_radial_expansion for
+ * an upstream gradient grad_c = dL/dc (chain rule through Eq. expansion and
+ * the Cartesian derivatives of Eq. iter-deri):
+ *   grad_R[j, l, n] = sum_m grad_c[e, n, l^2+l+m] * Y_l^m(xyz[j])
+ *   grad_xyz[j, a]  = sum_{n,k} grad_c[e, n, k] * R[j, l(k), n]
+ *                     * dY_k/dx_a(xyz[j])
+ * for the environment e holding point j.  Neither Y nor dY is stored.
+ *   xyz, offsets, n_env, n_points, R, l_max, normalize, dtype, status:
+ *              as in sph_radial_expansion
+ *   n_max      radial channels, 1 .. 16
+ *   grad_c     in  [n_env, n_max, (l_max+1)^2]
+ *   grad_xyz   out [n_points, 3]              (may be NULL)
+ *   grad_R     out [n_points, l_max+1, n_max] (may be NULL)
+ * Rows of points outside every environment's range (possible only with
+ * inconsistent offsets) are not written.  SPH_ERR_INVALID if the block's
+ * LDS (the environment's grad_c and one row per thread) would exceed
+ * 160 KiB (double l_max >= 28 with more than 8 channels).
+ */
+int32_t sph_radial_expansion_backward(const void* xyz, const int64_t* offsets, int64_t n_env,
+                                      int64_t n_points, const void* R, int32_t n_max,
+                                      int32_t l_max, int32_t normalize, int32_t dtype,
+                                      const void* grad_c, void* grad_xyz, void* grad_R,
+                                      int32_t* status, void* stream);
+
+/*
  * sph_batched_set_options -- batched-path controls (process-wide).
  *   use_graph  1: replay cached hipGraphs (default); 0: plain launches
  *   autotune   1: time the candidate launches on first use (default);

@@ -27,6 +27,7 @@ from ._native import (  # noqa: F401
     sph_compute_with_gradients,
     sph_double_backward,
     sph_radial_expansion,
+    sph_radial_expansion_backward,
     version,
 )
 from .autograd import (  # noqa: F401

@@ -46,6 +46,8 @@ _SIGNATURES = {
     "sph_double_backward": (_i32, [_vp, _vp, _vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp]),
     "sph_batched_compute": (_i32, [_vp, _vp, _i64, _i64, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "sph_radial_expansion": (_i32, [_vp, _vp, _i64, _i64, _vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp]),
+    "sph_radial_expansion_backward": (_i32, [_vp, _vp, _i64, _i64, _vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp,
+                                              _vp, _vp]),
     "sph_batched_set_options": (_i32, [_i32, _i32]),
     "sph_batched_get_config": (_i32, [_i32, _i32, _i32, _i32, _i32, ctypes.c_char_p, _i32]),
     "sph_batched_set_config": (_i32, [_i32, _i32, _i32, _i32, _i32, _i32, _i32]),
@@ -277,6 +279,38 @@ def sph_radial_expansion(xyz: torch.Tensor, offsets: torch.Tensor, R: torch.Tens
                                           int(bool(normalize)), _dtype_code(xyz), _ptr(c), _ptr(status),
                                           _stream(xyz.device)))
     return c
+
+
+def sph_radial_expansion_backward(xyz: torch.Tensor, offsets: torch.Tensor, R: torch.Tensor, grad_c: torch.Tensor,
+                                  l_max: int, normalize: bool = True, want_grad_xyz: bool = True,
+                                  want_grad_R: bool = True, status: torch.Tensor | None = None):
+    """(grad_xyz [n,3] or None, grad_R [n, l_max+1, n_max] or None) for an
+    upstream gradient grad_c [n_env, n_max, K] of sph_radial_expansion
+    (include/sph.h: sph_radial_expansion_backward)."""
+    _check_xyz(xyz)
+    n = xyz.shape[0]
+    K = (int(l_max) + 1) ** 2
+    if offsets.dtype != torch.int64 or offsets.dim() != 1 or offsets.device != xyz.device \
+            or not offsets.is_contiguous():
+        raise ValueError("offsets must be a contiguous int64 [n_env+1] tensor on the device of xyz")
+    n_env = offsets.shape[0] - 1
+    if n_env < 0:
+        raise ValueError("offsets needs at least one entry")
+    if R.dim() != 3:
+        raise ValueError("R must be [n_points, l_max+1, n_max]")
+    n_max = R.shape[2]
+    _need(R, "R", (n, int(l_max) + 1, n_max), xyz.dtype, xyz.device)
+    _need(grad_c, "grad_c", (n_env, n_max, K), xyz.dtype, xyz.device)
+    gx = torch.empty((n, 3), dtype=xyz.dtype, device=xyz.device) if want_grad_xyz else None
+    gR = torch.empty_like(R) if want_grad_R else None
+    if status is not None:
+        _need(status, "status", (1,), torch.int32, xyz.device)
+    with torch.cuda.device(xyz.device):
+        _check(lib().sph_radial_expansion_backward(_ptr(xyz), _ptr(offsets), n_env, n, _ptr(R), int(n_max),
+                                                   int(l_max), int(bool(normalize)), _dtype_code(xyz),
+                                                   _ptr(grad_c), _ptr(gx), _ptr(gR), _ptr(status),
+                                                   _stream(xyz.device)))
+    return gx, gR
 
 
 def sph_batched_set_options(use_graph: bool = True, autotune: bool = True):

@@ -460,6 +460,44 @@ int32_t sph_radial_expansion(const void* xyz, const int64_t* offsets, int64_t n_
   return ok();
 }
 
+int32_t sph_radial_expansion_backward(const void* xyz, const int64_t* offsets, int64_t n_env, int64_t n_points,
+                                      const void* R, int32_t n_max, int32_t l_max, int32_t normalize,
+                                      int32_t dtype, const void* grad_c, void* grad_xyz, void* grad_R,
+                                      int32_t* status, void* stream) {
+  int32_t st = check_common(n_points, l_max, dtype);
+  if (st != SPH_OK) return st;
+  if ((st = check_norm(normalize)) != SPH_OK) return st;
+  if (n_env < 0) return fail(SPH_ERR_INVALID, "n_env must be >= 0");
+  if (n_max < 1 || n_max > 16) return fail(SPH_ERR_INVALID, "n_max must be in [1, 16]");
+  if (offsets == nullptr) return fail(SPH_ERR_NULL, "offsets is required");
+  if (n_env > 0 && grad_c == nullptr) return fail(SPH_ERR_NULL, "grad_c is required");
+  if (n_points > 0 && (xyz == nullptr || R == nullptr)) return fail(SPH_ERR_NULL, "xyz and R are required");
+  if ((n_env == 0 || (grad_xyz == nullptr && grad_R == nullptr)) && status == nullptr) return ok();
+  const size_t w = elem_size(dtype);
+  const size_t K = static_cast<size_t>(sph_num_components(l_max));
+  const size_t un = static_cast<size_t>(n_points), ue = static_cast<size_t>(n_env);
+  const size_t nr = static_cast<size_t>(l_max + 1) * static_cast<size_t>(n_max);
+  const size_t sb = status ? size_t(4) : size_t(0);
+  if ((st = check_no_overlap({{grad_xyz, un * 3 * w, "grad_xyz"}, {grad_R, un * nr * w, "grad_R"},
+                              {status, sb, "status"}},
+                             {{xyz, un * 3 * w, "xyz"}, {R, un * nr * w, "R"}, {offsets, (ue + 1) * 8, "offsets"},
+                              {grad_c, ue * n_max * K * w, "grad_c"}, {grad_xyz, un * 3 * w, "grad_xyz"},
+                              {grad_R, un * nr * w, "grad_R"}, {status, sb, "status"}})) != SPH_OK)
+    return st;
+  const sph::KernelInfo ki = dtype == SPH_F64 ? sph::expand_bwd_info_f64(l_max, normalize, n_max)
+                                              : sph::expand_bwd_info_f32(l_max, normalize, n_max);
+  if (ki.fn == nullptr) return fail(SPH_ERR_INVALID, "no kernel for these arguments");
+  if (ki.lds_bytes > 160 * 1024) return fail(SPH_ERR_INVALID, "l_max and n_max need more LDS than one block has");
+  hipError_t e = ensure_lds(ki.fn, ki.lds_bytes);
+  if (e != hipSuccess) return device_fail(e, "hipFuncSetAttribute");
+  sph::ExpandBwdParams p{xyz, R, offsets, n_env, n_points, l_max, n_max, grad_c, grad_xyz, grad_R, status};
+  const int64_t resident = static_cast<int64_t>(num_cus()) * resident_per_cu(ki.fn, ki.block, ki.lds_bytes);
+  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(n_env, std::max<int64_t>(resident, 1)));
+  e = launch(ki.fn, static_cast<unsigned>(grid), ki.block, ki.lds_bytes, &p, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_fail(e, "radial expansion backward launch");
+  return ok();
+}
+
 int32_t sph_batched_set_options(int32_t use_graph, int32_t autotune) {
   if ((use_graph != 0 && use_graph != 1) || (autotune != 0 && autotune != 1))
     return fail(SPH_ERR_INVALID, "options must be 0 or 1");

@@ -220,4 +220,113 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandParams P) {
   }
 }
 
+// Backward of the expansion for an upstream gradient G = dL/dc (chain rule):
+//   grad_R[j, l, n] = sum_m G[e, n, l^2+l+m] Y_l^m(x_j)
+//   grad_xyz[j, a]  = sum_k gY[j, k] dY_k/dx_a(x_j),
+//                     gY[j, k] = sum_n G[e, n, k] R[j, l(k), n]
+// One thread per point, the environment's G in LDS ([k][channel], read as
+// 16-byte vectors, the same address for every thread).  Degree by degree the
+// thread forms the value row (grad_R and gY of the row, gY kept in its LDS
+// row) and then the three derivative rows (Eq. iter-deri), so neither Y nor
+// dY is stored.  NPC: channels padded to a multiple of 4 held in registers.
+template <typename T, int MM, int LT, bool NORM, int NPC>
+__global__ __launch_bounds__(kExpandThreads) void k_expand_bwd(ExpandBwdParams P) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int M = LT >= 0 ? LT : MM;
+  constexpr bool CT = LT >= 0;
+  using V = typename Vec16<T>::type;
+  constexpr int W = Vec16<T>::n;
+  const int tid = threadIdx.x;
+  const int L = LT >= 0 ? LT : P.L;
+  const int K = (L + 1) * (L + 1);
+  const int NM = P.n_max;
+  const int TS = (2 * L + 1) | 1;
+  T* sG = reinterpret_cast<T*>(smem);
+  T* sT = sG + static_cast<size_t>(K) * NPC + tid * TS;  // this thread's row
+  const T* xyz = static_cast<const T*>(P.xyz);
+  const T* R = static_cast<const T*>(P.R);
+  const T* gc = static_cast<const T*>(P.gc);
+  T* gxyz = static_cast<T*>(P.gxyz);
+  T* gR = static_cast<T*>(P.gR);
+
+  if (P.status != nullptr && blockIdx.x == 0 && tid < kWave) {
+    bool ok = true;
+    for (int64_t i = tid; i < P.n_env; i += kWave) ok = ok && (P.offsets[i] <= P.offsets[i + 1]);
+    if (tid == 0) ok = ok && P.offsets[0] == 0 && P.offsets[P.n_env] == P.n;
+    const bool all_ok = __all(ok);
+    if (tid == 0) P.status[0] = all_ok ? 0 : 4 /* SPH_ERR_OFFSETS */;
+  }
+
+  for (int64_t e = blockIdx.x; e < P.n_env; e += gridDim.x) {
+    int64_t b, t;
+    env_range(P.offsets, e, P.n, b, t);
+    if (t == b) continue;
+    __syncthreads();  // the previous environment's G is no longer read
+    const T* ge = gc + e * NM * K;
+    for (int i = tid; i < NPC * K; i += kExpandThreads) {
+      const int n = i / K;
+      const int k = i - n * K;
+      sG[k * NPC + n] = n < NM ? ge[i] : T(0);
+    }
+    __syncthreads();
+    for (int64_t j = b + tid; j < t; j += kExpandThreads) {
+      const Point<T> pt = make_point<T, NORM>(xyz[j * 3], xyz[j * 3 + 1], xyz[j * 3 + 2]);
+      T prev[M + 3], cur[M + 3];
+#pragma unroll
+      for (int m = 0; m < M + 3; ++m) prev[m] = T(0);
+      T g0 = T(0), g1 = T(0), g2 = T(0);
+      const T* Rj = R + j * (L + 1) * NM;
+      auto row = [&](int l) {
+        q_row_any<T, M, CT>(l, pt.ez, pt.rxy2, cur);
+        T r[NPC], acc[NPC];
+#pragma unroll
+        for (int n = 0; n < NPC; ++n) {
+          r[n] = n < NM ? Rj[l * NM + n] : T(0);
+          acc[n] = T(0);
+        }
+        const int kb = l * l;
+        emit_row<T, M, 0, NORM>(l, prev, cur, pt.ex, pt.ey, pt.ez, pt.inv_r, [&](int k, T v) {
+          const V* gv = reinterpret_cast<const V*>(sG + k * NPC);
+          T gy = T(0);
+#pragma unroll
+          for (int h = 0; h < NPC / W; ++h) {
+            const V g = gv[h];
+#pragma unroll
+            for (int u = 0; u < W; ++u) {
+              gy += g[u] * r[h * W + u];
+              acc[h * W + u] += g[u] * v;
+            }
+          }
+          sT[k - kb] = gy;
+        });
+        if (gR != nullptr) {
+          T* out = gR + (j * (L + 1) + l) * NM;
+#pragma unroll
+          for (int n = 0; n < NPC; ++n)
+            if (n < NM) out[n] = acc[n];
+        }
+        emit_row<T, M, 1, NORM>(l, prev, cur, pt.ex, pt.ey, pt.ez, pt.inv_r,
+                                [&](int k, T d) { g0 += sT[k - kb] * d; });
+        emit_row<T, M, 2, NORM>(l, prev, cur, pt.ex, pt.ey, pt.ez, pt.inv_r,
+                                [&](int k, T d) { g1 += sT[k - kb] * d; });
+        emit_row<T, M, 3, NORM>(l, prev, cur, pt.ex, pt.ey, pt.ez, pt.inv_r,
+                                [&](int k, T d) { g2 += sT[k - kb] * d; });
+#pragma unroll
+        for (int m = 0; m < M + 3; ++m) prev[m] = cur[m];  // row l - 1 of the next degree
+      };
+      if constexpr (CT) {
+#pragma unroll
+        for (int l = 0; l <= LT; ++l) row(l);
+      } else {
+        for (int l = 0; l <= L; ++l) row(l);
+      }
+      if (gxyz != nullptr) {
+        gxyz[j * 3 + 0] = g0;
+        gxyz[j * 3 + 1] = g1;
+        gxyz[j * 3 + 2] = g2;
+      }
+    }
+  }
+}
+
 }  // namespace sph

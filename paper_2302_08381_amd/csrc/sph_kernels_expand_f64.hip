@@ -10,6 +10,9 @@ using T = double;
 
 // l_max <= 8: compile-time degrees; larger: the run-time-degree kernel of
 // the m-extent bucket.
+// The backward unrolls four rows per degree: compile-time degrees up to 8
+// (beyond that the fully unrolled kernel spills).
+constexpr int kBwdSpecMax = 8;
 constexpr int kSpecMax = 8;
 
 template <bool NORM, int ACC, int... Is>
@@ -24,10 +27,32 @@ void fill_spec(const void** out, std::integer_sequence<int, Ls...>) {
   for (size_t i = 0; i < sizeof...(Ls); ++i) out[i] = tbl[i];
 }
 
+template <bool NORM, int NPC, int... Is>
+void fill_bwd(const void** out, std::integer_sequence<int, Is...>) {
+  const void* tbl[] = {reinterpret_cast<const void*>(&k_expand_bwd<T, kBuckets[Is], -1, NORM, NPC>)...};
+  for (size_t i = 0; i < sizeof...(Is); ++i) out[i] = tbl[i];
+}
+
+template <bool NORM, int NPC, int... Ls>
+void fill_bwd_spec(const void** out, std::integer_sequence<int, Ls...>) {
+  const void* tbl[] = {reinterpret_cast<const void*>(&k_expand_bwd<T, Ls, Ls, NORM, NPC>)...};
+  for (size_t i = 0; i < sizeof...(Ls); ++i) out[i] = tbl[i];
+}
+
 struct Tables {
   const void* fn[2][2][kNumBuckets];  // [normalize][ACC == 8]
   const void* spec[2][2][kSpecMax + 1];
+  const void* bwd[2][2][kNumBuckets];  // [normalize][NPC == 16]
+  const void* bwd_spec[2][2][kBwdSpecMax + 1];
   Tables() {
+    fill_bwd<false, 8>(bwd[0][0], std::make_integer_sequence<int, kNumBuckets>{});
+    fill_bwd<true, 8>(bwd[1][0], std::make_integer_sequence<int, kNumBuckets>{});
+    fill_bwd<false, 16>(bwd[0][1], std::make_integer_sequence<int, kNumBuckets>{});
+    fill_bwd<true, 16>(bwd[1][1], std::make_integer_sequence<int, kNumBuckets>{});
+    fill_bwd_spec<false, 8>(bwd_spec[0][0], std::make_integer_sequence<int, kBwdSpecMax + 1>{});
+    fill_bwd_spec<true, 8>(bwd_spec[1][0], std::make_integer_sequence<int, kBwdSpecMax + 1>{});
+    fill_bwd_spec<false, 16>(bwd_spec[0][1], std::make_integer_sequence<int, kBwdSpecMax + 1>{});
+    fill_bwd_spec<true, 16>(bwd_spec[1][1], std::make_integer_sequence<int, kBwdSpecMax + 1>{});
     fill_expand<false, 4>(fn[0][0], std::make_integer_sequence<int, kNumBuckets>{});
     fill_expand<true, 4>(fn[1][0], std::make_integer_sequence<int, kNumBuckets>{});
     fill_expand<false, 8>(fn[0][1], std::make_integer_sequence<int, kNumBuckets>{});
@@ -39,14 +64,29 @@ struct Tables {
   }
 };
 
+const Tables& tables() {
+  static const Tables t;
+  return t;
+}
+
 }  // namespace
 
 KernelInfo expand_info_f64(int L, int normalize, int n_max) {
-  static const Tables t;
+  const Tables& t = tables();
   if (L < 0 || L > kMaxLmax || (normalize != 0 && normalize != 1) || n_max < 1) return KernelInfo{nullptr, 0, 0, 0, 0};
   const int a = expand_acc(L, n_max) == 8 ? 1 : 0;
   const void* fn = L <= kSpecMax ? t.spec[normalize][a][L] : t.fn[normalize][a][bucket_index(L)];
   return KernelInfo{fn, 0, 0, 0, kExpandThreads};
+}
+
+KernelInfo expand_bwd_info_f64(int L, int normalize, int n_max) {
+  if (L < 0 || L > kMaxLmax || (normalize != 0 && normalize != 1) || n_max < 1 || n_max > 16)
+    return KernelInfo{nullptr, 0, 0, 0, 0};
+  const Tables& t = tables();
+  const int w = n_max > 8 ? 1 : 0;
+  const void* fn = L <= kBwdSpecMax ? t.bwd_spec[normalize][w][L] : t.bwd[normalize][w][bucket_index(L)];
+  const int npc = w ? 16 : 8;
+  return KernelInfo{fn, expand_bwd_lds_bytes<T>(L, npc), 0, npc, kExpandThreads};
 }
 
 }  // namespace sph

@@ -83,6 +83,28 @@ __host__ __device__ constexpr size_t expand_lds_bytes(int L, int n_max, int chun
   return ytile + sizeof(T) * (static_cast<size_t>(chunk) * (L + 1) * np + static_cast<size_t>(np) * K);
 }
 
+// Backward of the radial expansion (k_expand_bwd).
+struct ExpandBwdParams {
+  const void* xyz;         // [n,3]
+  const void* R;           // [n, L+1, n_max]
+  const int64_t* offsets;  // [n_env+1]
+  int64_t n_env;
+  int64_t n;
+  int32_t L;
+  int32_t n_max;
+  const void* gc;          // [n_env, n_max, K] upstream gradient of c
+  void* gxyz;              // [n,3] or null
+  void* gR;                // [n, L+1, n_max] or null
+  int32_t* status;         // device status word or null
+};
+// LDS of one backward block: the environment's upstream gradient [K][np]
+// and one row of per-degree partial results per thread.
+template <typename T>
+__host__ __device__ constexpr size_t expand_bwd_lds_bytes(int L, int np) {
+  const int K = (L + 1) * (L + 1);
+  return sizeof(T) * (static_cast<size_t>(K) * np + 128 * static_cast<size_t>((2 * L + 1) | 1));
+}
+
 // A kernel's host stub, its dynamic LDS bytes (for the l_max it was looked
 // up with), and for the forward with derivatives the LDS bytes when the
 // backward is fused (the extra upstream-gradient tile); tile_points is the
@@ -143,5 +165,9 @@ KernelInfo dbwd_info_f64(int L, int normalize);
 // expand_lds_bytes), block = 128 threads.
 KernelInfo expand_info_f32(int L, int normalize, int n_max);
 KernelInfo expand_info_f64(int L, int normalize, int n_max);
+// Its backward: channels padded to 8 or 16 (n_max <= 16); tile_points holds
+// the padded channel count.
+KernelInfo expand_bwd_info_f32(int L, int normalize, int n_max);
+KernelInfo expand_bwd_info_f64(int L, int normalize, int n_max);
 
 }  // namespace sph

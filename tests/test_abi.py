@@ -142,3 +142,15 @@ def test_radial_expansion_validation(lib):
     # l_max = 32 with 64 double channels: the 8-point chunk needs > 160 KiB of LDS
     assert x(FAKE, FAKE, 3, 10, FAKE, 64, 32, 1, 1, FAKE, None, None) == 2
     assert b"LDS" in lib.sph_last_error()
+
+
+def test_radial_expansion_backward_validation(lib):
+    x = lib.sph_radial_expansion_backward
+    #        xyz   offs  n_env n   R     n_max L  norm dt gc    gx    gR    status stream
+    assert x(FAKE, None, 3, 10, FAKE, 8, 4, 1, 0, FAKE, FAKE, None, None, None) == 1    # offsets NULL
+    assert x(FAKE, FAKE, 3, 10, FAKE, 17, 4, 1, 0, FAKE, FAKE, None, None, None) == 2   # n_max > 16
+    assert x(FAKE, FAKE, 3, 10, FAKE, 8, 4, 1, 0, None, FAKE, None, None, None) == 1    # grad_c NULL
+    assert x(FAKE, FAKE, 3, 10, FAKE, 8, 40, 1, 0, FAKE, FAKE, None, None, None) == 3   # l_max
+    assert x(FAKE, FAKE, 3, 10, FAKE, 8, 4, 1, 0, FAKE, None, None, None, None) == 0    # nothing requested
+    assert x(FAKE, FAKE, 3, 10, FAKE, 16, 30, 1, 1, FAKE, FAKE, None, None, None) == 2  # LDS
+    assert b"LDS" in lib.sph_last_error()

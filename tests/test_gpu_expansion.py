@@ -157,3 +157,81 @@ def test_expansion_status_and_degenerate_inputs():
     ref = np.zeros(25)
     ref[0] = 0.5 / np.sqrt(np.pi)
     assert np.allclose(c.cpu().numpy()[0, 0], ref, rtol=1e-6, atol=0)
+
+
+def _check_backward(gx, gR, pts, offs, R, G, l_max, normalize, dt, label=""):
+    """Scaled bounds as for the expansion: grad_R[j,l,n] sums 2l+1 terms
+    G Y (scale sum_m |G| s_l); grad_xyz[j,a] sums K terms gY dY with
+    gY = sum_n G R (scale sum_k (sum_n |G||R|) g_l), each with the
+    harmonics' error plus roundings of the sums."""
+    ref_x, ref_R = oracle.radial_expansion_backward(pts, offs, R, G, l_max, normalize)
+    ref_x, ref_R = np.asarray(ref_x, float), np.asarray(ref_R, float)
+    s, g, _ = oracle.component_scales(pts, l_max, normalize)
+    K = (l_max + 1) ** 2
+    lk = np.array([l for l in range(l_max + 1) for _ in range(2 * l + 1)])
+    env = np.repeat(np.arange(offs.size - 1), np.diff(offs))
+    Ga = np.abs(G)[env]                                            # [N, n, K]
+    Ra = np.abs(R)[:, lk, :]                                       # [N, K, n]
+    gys = np.einsum("jnk,jkn->jk", Ga, Ra)                        # bound of |gY|
+    nm = R.shape[2]
+    tol = TOL[dt] + (K + nm) * EPS[dt]
+    if gx is not None:
+        scale = (gys * g).sum(1)[:, None] + 1e-300
+        err = np.abs(gx.cpu().double().numpy() - ref_x) / scale
+        assert np.isfinite(err).all() and err.max() <= tol, (label, "grad_xyz", float(err.max()), tol)
+    if gR is not None:
+        sc = np.zeros_like(ref_R)
+        for l in range(l_max + 1):
+            sc[:, l, :] = (Ga[:, :, l * l:(l + 1) ** 2] * s[:, None, l * l:(l + 1) ** 2]).sum(2)
+        err = np.abs(gR.cpu().double().numpy() - ref_R) / (sc + 1e-300)
+        assert np.isfinite(err).all() and err.max() <= tol, (label, "grad_R", float(err.max()), tol)
+
+
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+@pytest.mark.parametrize("l_max,n_max,normalize", [
+    (0, 1, True), (2, 3, False), (4, 8, True), (8, 8, True), (8, 5, False), (8, 16, True), (11, 4, True),
+    (20, 9, True)])
+def test_expansion_backward_matches_oracle(dt, l_max, n_max, normalize):
+    import paper_2302_08381_amd as sph
+    print(f"expansion backward {dt} l_max={l_max} n_max={n_max} normalize={normalize}", flush=True)
+    counts = [0, 1, 7, 64, 129, 0, 200] if l_max <= 12 else [0, 1, 9, 40]
+    pts, offs, R = _case(counts, l_max, n_max, 500 + 7 * l_max + n_max)
+    xyz = to_dev(pts, dt)
+    Rt = to_dev(R, dt)
+    G = standard_normal((offs.size - 1, n_max, (l_max + 1) ** 2), 600 + l_max)
+    Gt = to_dev(G, dt)
+    st = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    o = torch.as_tensor(offs, device="cuda")
+    gx, gR = sph.sph_radial_expansion_backward(xyz, o, Rt, Gt, l_max, normalize, status=st)
+    only_x, none_R = sph.sph_radial_expansion_backward(xyz, o, Rt, Gt, l_max, normalize, want_grad_R=False)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0 and none_R is None
+    assert torch.equal(only_x, gx)
+    _check_backward(gx, gR, host_points(xyz), offs, Rt.cpu().double().numpy(), Gt.cpu().double().numpy(),
+                    l_max, normalize, dt, f"{dt} L={l_max} n={n_max}")
+
+
+def test_expansion_backward_through_autograd_matches_torch():
+    """The backward against torch autograd of the unfused composition in
+    float64 (harmonics from sph_compute_with_gradients, contracted by torch)."""
+    import paper_2302_08381_amd as sph
+    dt = torch.float64
+    L, NM = 6, 8
+    pts, offs = csr_environments(300, 8, 128, 0.5, 5.0, SEEDS["batched"] + 3)
+    xyz = to_dev(pts, dt)
+    o = torch.as_tensor(offs, device="cuda")
+    R = to_dev(gaussian_radial_basis(pts, L, NM, 5.0), dt)
+    G = to_dev(standard_normal((offs.size - 1, NM, (L + 1) ** 2), 77), dt)
+    gx, gR = sph.sph_radial_expansion_backward(xyz, o, R, G, L, True)
+    Y, dY = sph.sph_compute_with_gradients(xyz, L, True)
+    env = torch.repeat_interleave(torch.arange(offs.size - 1, device="cuda"), o[1:] - o[:-1])
+    lk = torch.tensor([l for l in range(L + 1) for _ in range(2 * l + 1)], device="cuda")
+    gY = (G[env] * R[:, lk, :].permute(0, 2, 1)).sum(1)           # [N, K]
+    ref_x = (gY[:, None, :] * dY).sum(2)
+    ref_R = torch.zeros_like(R)
+    prod = (G[env] * Y[:, None, :])                                  # [N, n, K]
+    for l in range(L + 1):
+        ref_R[:, l, :] = prod[:, :, l * l:(l + 1) ** 2].sum(2)
+    torch.cuda.synchronize()
+    assert float((gx - ref_x).abs().max()) <= 1e-10 * (1 + float(ref_x.abs().max()))
+    assert float((gR - ref_R).abs().max()) <= 1e-10 * (1 + float(ref_R.abs().max()))
