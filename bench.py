@@ -364,8 +364,9 @@ def main():
         summarize(args.summarize)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path has no "
-              "cross-GPU step and this build runs on a single MI355X.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the path has no "
+              "cross-GPU step; each GPU would run the same kernels on its own shard of points.",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
