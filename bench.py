@@ -348,6 +348,76 @@ def extras(dev):
     return out
 
 
+EXPANSION_PROFILE_COMMAND = ("rocprofv3 --kernel-trace --stats --output-format csv -d {out}/prof_expand -o run -- "
+                             "python3 {repo}/bench.py --profile-expansion --steps 20 --warmup 3")
+EXPANSION_L, EXPANSION_CHANNELS = 8, 8
+
+
+def _expansion_inputs(dev):
+    import numpy as np
+    import torch
+
+    from workloads import SEEDS, csr_environments, gaussian_radial_basis, standard_normal
+    pts, offs = csr_environments(20_000, 8, 128, 0.5, 5.0, SEEDS["batched"])
+    K = (EXPANSION_L + 1) ** 2
+    xyz = torch.as_tensor(pts, dtype=torch.float32).to(dev)
+    o = torch.as_tensor(offs, device=dev)
+    R = torch.as_tensor(gaussian_radial_basis(pts, EXPANSION_L, EXPANSION_CHANNELS, 5.0), dtype=torch.float32).to(dev)
+    G = torch.as_tensor(standard_normal((offs.size - 1, EXPANSION_CHANNELS, K), 700 + EXPANSION_L),
+                        dtype=torch.float32).to(dev)
+    return xyz, o, R, G, int(offs[-1]), int(np.asarray(offs).size - 1)
+
+
+def profile_expansion(dev, steps: int, warmup: int) -> None:
+    import torch
+
+    import paper_2302_08381_amd as sph
+    xyz, o, R, G, n, n_env = _expansion_inputs(dev)
+    c = torch.empty((n_env, EXPANSION_CHANNELS, (EXPANSION_L + 1) ** 2), device=dev)
+
+    def step():
+        sph.sph_radial_expansion(xyz, o, R, EXPANSION_L, True, out=c)
+        sph.sph_radial_expansion_backward(xyz, o, R, G, EXPANSION_L, True)
+    for _ in range(warmup + steps):
+        step()
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_run": "radial_expansion", "steps": steps, "points": n, "environments": n_env}))
+
+
+def summarize_expansion(outdir: str) -> None:
+    """profiles/expansion_l8_f32.md: kernel-trace means of the radial
+    expansion and its backward over the timed launches, with their
+    algorithmic bytes."""
+    import csv
+    from workloads import SEEDS, csr_environments
+    _, offs = csr_environments(20_000, 8, 128, 0.5, 5.0, SEEDS["batched"])
+    n, n_env = int(offs[-1]), offs.size - 1
+    L, NM = EXPANSION_L, EXPANSION_CHANNELS
+    K = (L + 1) ** 2
+    fwd_bytes = n * 4 * (3 + (L + 1) * NM) + n_env * (8 + 4 * NM * K)
+    bwd_bytes = n * 4 * (3 + 2 * (L + 1) * NM + 3) + n_env * (8 + 4 * NM * K)
+    with open(os.path.join(outdir, "prof_expand", "run_kernel_trace.csv")) as f:
+        trace = list(csv.DictReader(f))
+    cmd = EXPANSION_PROFILE_COMMAND.format(out="/root/repo/gpurun_out", repo="/root/repo")
+    lines = [f"# Kernel trace: radial expansion and its backward, l_max = {L}, {NM} channels, float32, "
+             f"{n_env} environments ({n} points)", "",
+             "Command (from /tmp, TMPDIR=/tmp):", "", "    " + cmd, "",
+             "Means over the last 20 launches of each kernel (the timed steps):", "",
+             "| kernel | launches | mean us | algorithmic bytes | algorithmic GB/s | points/s |",
+             "|---|---|---|---|---|---|"]
+    for tag, byts in (("k_expand<", fwd_bytes), ("k_expand_bwd<", bwd_bytes)):
+        rows = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"])
+                      for r in trace if tag in r["Kernel_Name"])[-20:]
+        if not rows:
+            continue
+        m = sum(e - b for b, e, _ in rows) / len(rows) * 1e-9
+        lines.append(f"| `{rows[0][2]}` | {len(rows)} | {m * 1e6:.1f} | {byts} | {byts / m / 1e9:.0f} | {n / m:.3g} |")
+    lines += ["", "Algorithmic bytes: forward N*4*(3 + (L+1)*n_max) + n_env*(8 + 4*n_max*K); backward "
+              "N*4*(3 + 2*(L+1)*n_max + 3) + n_env*(8 + 4*n_max*K)."]
+    with open(os.path.join(ROOT, "profiles", "expansion_l8_f32.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -359,9 +429,17 @@ def main():
                     help="only run warmup + steps (and a 1 GiB reference copy), for rocprofv3")
     ap.add_argument("--summarize", metavar="DIR",
                     help="write the profiles/ summaries from the rocprofv3 output in DIR (no GPU)")
+    ap.add_argument("--profile-expansion", action="store_true",
+                    help="only run the radial expansion and its backward (l_max = 8, the 20 000 batched "
+                         "environments, 8 channels, float32): warmup + steps, for rocprofv3")
+    ap.add_argument("--summarize-expansion", metavar="DIR",
+                    help="write profiles/expansion_l8_f32.md from the kernel trace in DIR/prof_expand (no GPU)")
     args = ap.parse_args()
     if args.summarize:
         summarize(args.summarize)
+        return
+    if args.summarize_expansion:
+        summarize_expansion(args.summarize_expansion)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the path has no "
@@ -376,6 +454,9 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.profile_expansion:
+        profile_expansion(dev, args.steps, args.warmup)
+        return
     K = (L_MAX + 1) ** 2
     xyz = torch.as_tensor(standard_normal_points(N_POINTS, SEEDS["plain_gpu"]), dtype=torch.float32).to(dev)
     gY = torch.as_tensor(standard_normal((N_POINTS, K), SEEDS["plain_gpu_grad"]), dtype=torch.float32).to(dev)
