@@ -1,12 +1,13 @@
 // Radial expansion over CSR environments (Sec. I, Eq. expansion):
 //   c[e, n, l^2+l+m] = sum over the points j of environment e of
 //                      R[j, l, n] * Y_l^m(x_j)
-// with the radial values R[j, l, n] supplied by the caller.  The harmonics
-// never leave the chip: one block takes one environment at a time, writes
-// the values of a chunk of its points into an LDS tile (one thread per
-// point, the values-only emission), copies the chunk's radial values next to
-// it, and contracts the two tiles into per-thread accumulators; partial sums
-// of environments longer than one chunk wait in LDS.
+// with the radial values R[j, l, n] supplied by the caller, and its
+// backward.  The harmonics never leave the chip.  Forward: a block takes one
+// environment at a time, writes the values of a chunk of its points into an
+// LDS tile, copies the chunk's radial values next to it, and contracts the
+// two tiles into per-thread accumulators; partial sums of environments
+// longer than one chunk wait in LDS.  Backward: one thread per point, see
+// k_expand_bwd.
 #pragma once
 
 #include "sph_device.hpp"
