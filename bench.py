@@ -345,6 +345,21 @@ def extras(dev):
                         "fused_points_per_s": nb / tex, "fused_GB_per_s": byts / tex / 1e9,
                         "backward_points_per_s": nb / tbw}
     out["radial_expansion_20k_envs_f32"] = exp
+    # compile-time (unrolled, literal coefficients) against run-time-degree
+    # kernels at low l_max: the batched path on the same environments, Y and
+    # dY stored, one tile per block, each variant pinned
+    spec = {}
+    for Ls in range(1, 7):
+        Ks = (Ls + 1) ** 2
+        o = {"Y": torch.empty((nb, Ks), device=dev), "dY": torch.empty((nb, 3, Ks), device=dev)}
+        row = {}
+        for variant in ("default", "runtime_degree"):
+            sph.sph_batched_set_config(Ls, True, torch.float32, True, False, variant, 0)
+            row[variant + "_s"] = _time(lambda: sph.sph_batched_compute(xc, oc, Ls, True, store_dY=True, out=o), 20)
+        row["GB_per_s_default"] = nb * 4 * (3 + 4 * Ks) / row["default_s"] / 1e9
+        sph.sph_batched_set_config(Ls, True, torch.float32, True, False, "default", 0)
+        spec[str(Ls)] = row
+    out["compile_time_vs_runtime_degree_f32"] = spec
     return out
 
 
