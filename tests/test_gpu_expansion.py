@@ -235,3 +235,36 @@ def test_expansion_backward_through_autograd_matches_torch():
     torch.cuda.synchronize()
     assert float((gx - ref_x).abs().max()) <= 1e-10 * (1 + float(ref_x.abs().max()))
     assert float((gR - ref_R).abs().max()) <= 1e-10 * (1 + float(ref_R.abs().max()))
+
+
+def test_expansion_deterministic_and_unaligned_inputs():
+    """No atomics: repeated calls are bitwise equal.  Inputs and outputs that
+    start at odd element offsets (not 16-byte aligned) give the same results."""
+    import paper_2302_08381_amd as sph
+    dt = torch.float32
+    L, NM = 8, 5
+    pts, offs, R = _case([3, 70, 0, 129, 33], L, NM, 909)
+    n, E, K = pts.shape[0], offs.size - 1, (L + 1) ** 2
+    xyz = to_dev(pts, dt)
+    Rt = to_dev(R, dt)
+    G = to_dev(standard_normal((E, NM, K), 910), dt)
+    o = torch.as_tensor(offs, device="cuda")
+    c1 = sph.sph_radial_expansion(xyz, o, Rt, L, True)
+    c2 = sph.sph_radial_expansion(xyz, o, Rt, L, True)
+    gx1, gR1 = sph.sph_radial_expansion_backward(xyz, o, Rt, G, L, True)
+    gx2, gR2 = sph.sph_radial_expansion_backward(xyz, o, Rt, G, L, True)
+    # the same values one element into larger buffers
+    bx = torch.empty(n * 3 + 1, dtype=dt, device="cuda")
+    bx[1:] = xyz.flatten()
+    bR = torch.empty(Rt.numel() + 1, dtype=dt, device="cuda")
+    bR[1:] = Rt.flatten()
+    bG = torch.empty(G.numel() + 1, dtype=dt, device="cuda")
+    bG[1:] = G.flatten()
+    bc = torch.empty(E * NM * K + 1, dtype=dt, device="cuda")
+    xu, Ru, Gu = bx[1:].view(n, 3), bR[1:].view(n, L + 1, NM), bG[1:].view(E, NM, K)
+    cu = sph.sph_radial_expansion(xu, o, Ru, L, True, out=bc[1:].view(E, NM, K))
+    gxu, gRu = sph.sph_radial_expansion_backward(xu, o, Ru, Gu, L, True)
+    torch.cuda.synchronize()
+    for a, b, name in ((c1, c2, "c"), (gx1, gx2, "grad_xyz"), (gR1, gR2, "grad_R"), (c1, cu, "c unaligned"),
+                       (gx1, gxu, "grad_xyz unaligned"), (gR1, gRu, "grad_R unaligned")):
+        assert torch.equal(a, b), name
