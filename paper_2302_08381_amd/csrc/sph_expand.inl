@@ -184,37 +184,116 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandParams P) {
     }
     __syncthreads();
     const bool last = c0 + JC >= ct;
-    for (int it = tid; it < items; it += kExpandThreads) {
-      const int g = it / K;
-      const int k = it - g * K;
-      int l = static_cast<int>(sqrtf(static_cast<float>(k)));
-      l += (l + 1) * (l + 1) <= k ? 1 : 0;
-      l -= l * l > k ? 1 : 0;
-      T a[ACC];
-#pragma unroll
-      for (int u = 0; u < ACC; ++u) a[u] = c0 == cb ? T(0) : sC[(g * ACC + u) * K + k];
+    bool done = false;
+    if constexpr (LT >= 0 && LT <= 4) {
+      // Fewer items than threads (small l_max): the chunk's points are split
+      // into S parts, each summed by its own thread; parts 1..S-1 leave their
+      // sums in the (then free) radial tile and part 0 adds them in order.
+      const int S = items > kExpandThreads / 2 ? 1
+                    : (items > kExpandThreads / 4 ? 2 : 4);
+      const bool split = S > 1 && JC * RS >= (S - 1) * items * ACC;
+      const int nparts = split ? S : 1;
+      const int jper = (cnt + nparts - 1) / nparts;
       using V = typename Vec16<T>::type;
       constexpr int W = Vec16<T>::n;
-      const T* yc = sY + k;
-      const T* rc = sR + l * NP + g * ACC;  // 16-byte aligned (NP, ACC multiples of 4)
+      auto item_sum = [&](int k, int g, int l, int ja, int jb, T (&a)[ACC]) {
+        const T* yc = sY + k;
+        const T* rc = sR + l * NP + g * ACC;  // 16-byte aligned (NP, ACC multiples of 4)
 #pragma unroll 4
-      for (int j = 0; j < cnt; ++j) {
-        const T yv = yc[j * SY];
-        const V* r = reinterpret_cast<const V*>(rc + j * RS);
+        for (int j = ja; j < jb; ++j) {
+          const T yv = yc[j * SY];
+          const V* r = reinterpret_cast<const V*>(rc + j * RS);
 #pragma unroll
-        for (int h = 0; h < ACC / W; ++h) {
-          const V rv = r[h];
+          for (int h = 0; h < ACC / W; ++h) {
+            const V rv = r[h];
 #pragma unroll
-          for (int u = 0; u < W; ++u) a[h * W + u] += rv[u] * yv;
+            for (int u = 0; u < W; ++u) a[h * W + u] += rv[u] * yv;
+          }
         }
+      };
+      auto degree_of = [](int k) {
+        int l = static_cast<int>(sqrtf(static_cast<float>(k)));
+        l += (l + 1) * (l + 1) <= k ? 1 : 0;
+        l -= l * l > k ? 1 : 0;
+        return l;
+      };
+      auto finish_item = [&](int k, int g, T (&a)[ACC]) {
+        if (last) {
+#pragma unroll
+          for (int u = 0; u < ACC; ++u)
+            if (g * ACC + u < NM) ce[(g * ACC + u) * K + k] = a[u];
+        } else {
+#pragma unroll
+          for (int u = 0; u < ACC; ++u) sC[(g * ACC + u) * K + k] = a[u];
+        }
+      };
+      if (split) {
+          const int it = tid % items;
+          const int part = tid / items;
+          const int g = it / K;
+          const int k = it - g * K;
+          T a[ACC];
+#pragma unroll
+          for (int u = 0; u < ACC; ++u) a[u] = T(0);
+          if (part < S) {
+            const int ja = part * jper;
+            const int jb = ja + jper < cnt ? ja + jper : cnt;
+            item_sum(k, g, degree_of(k), ja, jb, a);
+          }
+          __syncthreads();  // every read of the radial tile is done
+          T* sP = sR;
+          if (part >= 1 && part < S) {
+#pragma unroll
+            for (int u = 0; u < ACC; ++u) sP[((part - 1) * items + it) * ACC + u] = a[u];
+          }
+          __syncthreads();
+          if (part == 0) {
+            for (int q = 1; q < S; ++q) {
+#pragma unroll
+              for (int u = 0; u < ACC; ++u) a[u] += sP[((q - 1) * items + it) * ACC + u];
+            }
+            if (c0 != cb) {
+#pragma unroll
+              for (int u = 0; u < ACC; ++u) a[u] += sC[(g * ACC + u) * K + k];
+            }
+            finish_item(k, g, a);
+          }
+        done = true;
       }
-      if (last) {
+    }
+    if (!done) {
+      for (int it = tid; it < items; it += kExpandThreads) {
+        const int g = it / K;
+        const int k = it - g * K;
+        int l = static_cast<int>(sqrtf(static_cast<float>(k)));
+        l += (l + 1) * (l + 1) <= k ? 1 : 0;
+        l -= l * l > k ? 1 : 0;
+        T a[ACC];
 #pragma unroll
-        for (int u = 0; u < ACC; ++u)
-          if (g * ACC + u < NM) ce[(g * ACC + u) * K + k] = a[u];
-      } else {
+        for (int u = 0; u < ACC; ++u) a[u] = c0 == cb ? T(0) : sC[(g * ACC + u) * K + k];
+        using V = typename Vec16<T>::type;
+        constexpr int W = Vec16<T>::n;
+        const T* yc = sY + k;
+        const T* rc = sR + l * NP + g * ACC;  // 16-byte aligned (NP, ACC multiples of 4)
+#pragma unroll 4
+        for (int j = 0; j < cnt; ++j) {
+          const T yv = yc[j * SY];
+          const V* r = reinterpret_cast<const V*>(rc + j * RS);
 #pragma unroll
-        for (int u = 0; u < ACC; ++u) sC[(g * ACC + u) * K + k] = a[u];
+          for (int h = 0; h < ACC / W; ++h) {
+            const V rv = r[h];
+#pragma unroll
+            for (int u = 0; u < W; ++u) a[h * W + u] += rv[u] * yv;
+          }
+        }
+        if (last) {
+#pragma unroll
+          for (int u = 0; u < ACC; ++u)
+            if (g * ACC + u < NM) ce[(g * ACC + u) * K + k] = a[u];
+        } else {
+#pragma unroll
+          for (int u = 0; u < ACC; ++u) sC[(g * ACC + u) * K + k] = a[u];
+        }
       }
     }
     __syncthreads();
