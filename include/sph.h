@@ -27,8 +27,18 @@
  * - Errors: arguments are validated on the host before anything is
  *   enqueued.  On an error the call returns a non-zero sph_status_t, writes
  *   nothing, and sph_last_error() holds a message (per host thread).
- *   n = 0 (or n_env = 0) is valid and enqueues nothing.  A failed kernel
- *   launch returns SPH_ERR_DEVICE.
+ *   n = 0 (or n_env = 0) is valid and enqueues nothing (except a requested
+ *   status word, below).  A failed kernel launch returns SPH_ERR_DEVICE.
+ * - One exception: CSR offsets.  The offsets of the CSR entry points
+ *   (sph_batched_compute, sph_radial_expansion and its backward) live in
+ *   device memory, so the host does not read them: doing so would need a
+ *   device-to-host copy and a synchronisation on every call, which rules
+ *   out asynchronous launches and graph capture.  The kernel checks them
+ *   instead (offsets[0] == 0, non-decreasing, offsets[n_env] == n_points)
+ *   and writes SPH_OK or SPH_ERR_OFFSETS to the caller's optional status
+ *   word.  The call itself returns SPH_OK once the launch is enqueued; what
+ *   the outputs hold when the offsets are inconsistent is stated per entry
+ *   point.  A caller that passes no status word gets no report.
  * - Numerics: NaN/Inf inputs propagate to the outputs; they are not errors.
  *   At r = 0 the scaled harmonics take their polynomial values; the
  *   normalised ones return Y_0^0 = 1/(2 sqrt(pi)) and 0 for every other
@@ -135,11 +145,15 @@ int32_t sph_double_backward(const void* xyz, const void* grad_Y, const void* v,
  * owns rows offsets[e] .. offsets[e+1]-1 of xyz (Sec. III: the harmonics of
  * the neighbours of each selected atom).  Every output follows the
  * concatenated row order.  The launch is a persistent kernel replayed from a
- * cached hipGraph.  On the first call for a (dtype, l_max, normalize,
- * outputs) combination the library times its candidate launches on the
- * caller's own buffers and keeps the fastest; the timing synchronises the
- * host once.  The candidates are every kernel variant (the unrolled
- * compile-time kernel on its default tile, the same on a 16-point tile, the
+ * cached hipGraph: one graph per (dtype, l_max, normalize, outputs)
+ * combination and kernel, whose grid and arguments each call sets, so calls
+ * with a changing n_points reuse it.  On the first call for a combination
+ * with at least 16384 points, outside a stream capture, the library times
+ * its candidate launches on the caller's own buffers and keeps the fastest;
+ * the timing synchronises the host once.  Smaller or captured calls use the
+ * defaults and leave the combination to be tuned by a later call.  The
+ * candidates are every kernel variant (the unrolled compile-time kernel on
+ * its default tile, the same on a 16-point tile, the
  * run-time-degree kernel, the 16-point tile with its degrees split between
  * two waves) crossed with every persistent-grid size.
  *   xyz        in  [n_points,3]

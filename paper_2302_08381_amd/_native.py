@@ -130,6 +130,29 @@ def _check_xyz(xyz: torch.Tensor):
     _dtype_code(xyz)
 
 
+def _csr_status(status, check, device):
+    """(status word, whether the wrapper checks it) for a CSR call.  A
+    caller's status word is the caller's to read unless ``check`` is True;
+    without one the wrapper allocates a word and checks it unless ``check``
+    is False."""
+    if status is not None:
+        _need(status, "status", (1,), torch.int32, device)
+        return status, bool(check)
+    if check is False:
+        return None, False
+    return torch.empty((1,), dtype=torch.int32, device=device), True
+
+
+def _raise_on_status(status, check: bool):
+    """Synchronises on the status word and raises SphError(SPH_ERR_OFFSETS)
+    if the kernel found the offsets inconsistent."""
+    if check:
+        code = int(status.item())
+        if code != SPH_OK:
+            raise SphError(code, "inconsistent CSR offsets: offsets[0] must be 0, offsets non-decreasing "
+                                 "and offsets[n_env] equal to the number of points")
+
+
 def num_components(l_max: int) -> int:
     return int(lib().sph_num_components(int(l_max)))
 
@@ -212,12 +235,18 @@ def sph_double_backward(xyz: torch.Tensor, grad_Y: torch.Tensor, v: torch.Tensor
 
 def sph_batched_compute(xyz: torch.Tensor, offsets: torch.Tensor, l_max: int, normalize: bool = True,
                         store_dY: bool = True, grad_Y: torch.Tensor | None = None,
-                        status: torch.Tensor | None = None, out: dict | None = None):
+                        status: torch.Tensor | None = None, out: dict | None = None, check: bool | None = None):
     """Batched CSR evaluation (include/sph.h: sph_batched_compute).
 
     Returns a dict with "Y", "dY" (or None), "grad_xyz" (or None) and
     "status" (an int32[1] device tensor written by the kernel, or None).
     ``out`` may hold preallocated "Y", "dY", "grad_xyz" tensors.
+
+    The kernel checks the offsets on the device and writes its verdict to a
+    status word.  Without a ``status`` tensor of the caller's the wrapper
+    passes one of its own, waits for the call and raises SphError on
+    inconsistent offsets; ``check=False`` skips that (the call stays
+    asynchronous), ``check=True`` also checks a caller's status word.
     """
     _check_xyz(xyz)
     n = xyz.shape[0]
@@ -243,20 +272,21 @@ def sph_batched_compute(xyz: torch.Tensor, offsets: torch.Tensor, l_max: int, no
         gx = out.get("grad_xyz")
         gx = torch.empty((n, 3), dtype=xyz.dtype, device=xyz.device) if gx is None else \
             _need(gx, "grad_xyz", (n, 3), xyz.dtype, xyz.device)
-    if status is not None:
-        _need(status, "status", (1,), torch.int32, xyz.device)
+    status, check = _csr_status(status, check, xyz.device)
     with torch.cuda.device(xyz.device):
         _check(lib().sph_batched_compute(_ptr(xyz), _ptr(offsets), n_env, n, int(l_max), int(bool(normalize)),
                                          _dtype_code(xyz), _ptr(Y), _ptr(dY), _ptr(grad_Y), _ptr(gx),
                                          _ptr(status), _stream(xyz.device)))
+    _raise_on_status(status, check)
     return {"Y": Y, "dY": dY, "grad_xyz": gx, "status": status}
 
 
 def sph_radial_expansion(xyz: torch.Tensor, offsets: torch.Tensor, R: torch.Tensor, l_max: int,
                          normalize: bool = True, status: torch.Tensor | None = None,
-                         out: torch.Tensor | None = None) -> torch.Tensor:
+                         out: torch.Tensor | None = None, check: bool | None = None) -> torch.Tensor:
     """c[n_env, n_max, K] = sum over each environment's points of R[j,l,n] Y_l^m(x_j)
-    (include/sph.h: sph_radial_expansion).  R is [n_points, l_max+1, n_max]."""
+    (include/sph.h: sph_radial_expansion).  R is [n_points, l_max+1, n_max].
+    ``check`` as in sph_batched_compute."""
     _check_xyz(xyz)
     n = xyz.shape[0]
     K = (int(l_max) + 1) ** 2
@@ -272,21 +302,23 @@ def sph_radial_expansion(xyz: torch.Tensor, offsets: torch.Tensor, R: torch.Tens
     _need(R, "R", (n, int(l_max) + 1, n_max), xyz.dtype, xyz.device)
     c = torch.empty((n_env, n_max, K), dtype=xyz.dtype, device=xyz.device) if out is None else \
         _need(out, "out", (n_env, n_max, K), xyz.dtype, xyz.device)
-    if status is not None:
-        _need(status, "status", (1,), torch.int32, xyz.device)
+    status, check = _csr_status(status, check, xyz.device)
     with torch.cuda.device(xyz.device):
         _check(lib().sph_radial_expansion(_ptr(xyz), _ptr(offsets), n_env, n, _ptr(R), int(n_max), int(l_max),
                                           int(bool(normalize)), _dtype_code(xyz), _ptr(c), _ptr(status),
                                           _stream(xyz.device)))
+    _raise_on_status(status, check)
     return c
 
 
 def sph_radial_expansion_backward(xyz: torch.Tensor, offsets: torch.Tensor, R: torch.Tensor, grad_c: torch.Tensor,
                                   l_max: int, normalize: bool = True, want_grad_xyz: bool = True,
-                                  want_grad_R: bool = True, status: torch.Tensor | None = None):
+                                  want_grad_R: bool = True, status: torch.Tensor | None = None,
+                                  check: bool | None = None):
     """(grad_xyz [n,3] or None, grad_R [n, l_max+1, n_max] or None) for an
     upstream gradient grad_c [n_env, n_max, K] of sph_radial_expansion
-    (include/sph.h: sph_radial_expansion_backward)."""
+    (include/sph.h: sph_radial_expansion_backward).  ``check`` as in
+    sph_batched_compute."""
     _check_xyz(xyz)
     n = xyz.shape[0]
     K = (int(l_max) + 1) ** 2
@@ -303,13 +335,13 @@ def sph_radial_expansion_backward(xyz: torch.Tensor, offsets: torch.Tensor, R: t
     _need(grad_c, "grad_c", (n_env, n_max, K), xyz.dtype, xyz.device)
     gx = torch.empty((n, 3), dtype=xyz.dtype, device=xyz.device) if want_grad_xyz else None
     gR = torch.empty_like(R) if want_grad_R else None
-    if status is not None:
-        _need(status, "status", (1,), torch.int32, xyz.device)
+    status, check = _csr_status(status, check, xyz.device)
     with torch.cuda.device(xyz.device):
         _check(lib().sph_radial_expansion_backward(_ptr(xyz), _ptr(offsets), n_env, n, _ptr(R), int(n_max),
                                                    int(l_max), int(bool(normalize)), _dtype_code(xyz),
                                                    _ptr(grad_c), _ptr(gx), _ptr(gR), _ptr(status),
                                                    _stream(xyz.device)))
+    _raise_on_status(status, check)
     return gx, gR
 
 

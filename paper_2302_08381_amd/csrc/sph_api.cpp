@@ -192,18 +192,20 @@ const char* variant_name(int v) {
   }
 }
 
+// One instantiated single-node graph per (combination, kernel, LDS size).
+// The grid is not part of the key: every call rewrites the node's grid and
+// arguments, so a caller whose point count changes from call to call (a
+// neighbour list that changes every step) reuses one graph.  Every kernel
+// walks its tiles with a grid-stride loop, so any grid is correct.
 struct GraphEntry {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipGraphNode_t node = nullptr;
-  const void* fn = nullptr;
-  unsigned grid = 0;
-  size_t lds = 0;
 };
 
 std::mutex g_batch_mu;
 std::map<BatchKey, Choice> g_choice;
-std::map<std::tuple<BatchKey, const void*, unsigned, size_t>, GraphEntry> g_graphs;
+std::map<std::tuple<BatchKey, const void*, size_t>, GraphEntry> g_graphs;
 int g_use_graph = 1;
 int g_autotune = 1;
 bool g_cache_loaded = false;
@@ -590,9 +592,10 @@ int32_t sph_batched_compute(const void* xyz, const int64_t* offsets, int64_t n_e
     ch = autotune(dtype, l_max, normalize, dY != nullptr, bwd, p, s);
     g_choice[key] = ch;
     save_cache_locked();
-  } else {
-    g_choice[key] = ch;
   }
+  // Otherwise (tuning off, a capture in progress, or too few points to time)
+  // this call uses the defaults and records nothing, so a later large call
+  // outside a capture still tunes the combination.
   const sph::KernelInfo ki = fwd_info(dtype, l_max, normalize, dY != nullptr, bwd, ch.variant);
   if (ki.fn == nullptr) return fail(SPH_ERR_INVALID, "no kernel for the chosen variant");
   const size_t lds = bwd ? ki.lds_bytes_bwd : ki.lds_bytes;
@@ -606,9 +609,9 @@ int32_t sph_batched_compute(const void* xyz, const int64_t* offsets, int64_t n_e
     return ok();
   }
 
-  // One graph per (combination, kernel, grid, LDS); later calls update the
-  // kernel node's arguments and replay it.
-  auto gkey = std::make_tuple(key, ki.fn, grid, lds);
+  // One graph per (combination, kernel, LDS); later calls set the kernel
+  // node's grid and arguments and replay it.
+  auto gkey = std::make_tuple(key, ki.fn, lds);
   GraphEntry& g = g_graphs[gkey];
   void* args[] = {&p};
   hipKernelNodeParams np{};
@@ -630,9 +633,6 @@ int32_t sph_batched_compute(const void* xyz, const int64_t* offsets, int64_t n_e
       g = GraphEntry{};
       return device_fail(e, "hipGraphInstantiate");
     }
-    g.fn = ki.fn;
-    g.grid = grid;
-    g.lds = lds;
   } else {
     if ((e = hipGraphExecKernelNodeSetParams(g.exec, g.node, &np)) != hipSuccess)
       return device_fail(e, "hipGraphExecKernelNodeSetParams");

@@ -151,6 +151,66 @@ def test_batched_workload_autotuned_per_lmax():
         assert mx.max() <= TOL[torch.float32]
         mx, _ = oracle.per_l_errors(out["dY"][idx].cpu().numpy(), Gr, hp, L, True, "dY")
         assert mx.max() <= TOL[torch.float32]
+        # the fused backward's grad_xyz on the same rows
+        gYh = gY[idx].cpu().double().numpy()
+        _, g, _ = oracle.component_scales(hp, L, True)
+        err = np.abs(out["grad_xyz"][idx].cpu().double().numpy() - np.asarray(oracle.backward(Gr, gYh), float))
+        assert (err / (np.abs(gYh) * g).sum(1)[:, None]).max() <= TOL[torch.float32], L
+
+
+def test_batched_graph_reuse_across_changing_sizes():
+    """An MD-like loop: the number of neighbours changes every call.  The
+    cached graph of a combination is reused with the call's grid (one tile
+    per block, so the grid follows n_points up and down); every call equals
+    the plain kernel bitwise, and the fused backward the plain backward."""
+    import paper_2302_08381_amd as sph
+    L = 6
+    K = 49
+    sph.sph_batched_set_config(L, True, torch.float32, True, True, "default", 0)
+    sph.sph_batched_set_config(L, True, torch.float32, False, False, "default", 0)
+    rng = np.random.default_rng(123)
+    sizes = set()
+    for call in range(44):
+        n_env = int(rng.integers(1, 400))
+        pts, offs = csr_environments(n_env, 0, 128, 0.5, 5.0, 5000 + call)
+        n = int(offs[-1])
+        sizes.add(n)
+        print(f"graph reuse call {call}: n_env={n_env} n_points={n}", flush=True)
+        xyz = to_dev(pts, torch.float32)
+        gY = to_dev(standard_normal((n, K), 6000 + call), torch.float32)
+        o = _offsets(offs)
+        out = sph.sph_batched_compute(xyz, o, L, True, store_dY=True, grad_Y=gY)
+        vals = sph.sph_batched_compute(xyz, o, L, True, store_dY=False)
+        Y, dY = sph.sph_compute_with_gradients(xyz, L, True)
+        gx = sph.sph_backward(dY, gY, L)
+        torch.cuda.synchronize()
+        assert_bitwise_equal(out["Y"], Y, f"call {call} Y")
+        assert_bitwise_equal(out["dY"], dY, f"call {call} dY")
+        assert_bitwise_equal(vals["Y"], sph.sph_compute(xyz, L, True), f"call {call} values")
+        scale = (gY.abs().double()[:, None, :] * dY.abs().double()).sum(2) + 1e-30
+        assert float(((out["grad_xyz"].double() - gx.double()).abs() / scale).max()) < 1e-5, call
+    assert len(sizes) >= 40
+
+
+def test_batched_bad_offsets_raise_by_default():
+    """Without a status word of the caller's, the wrapper checks the
+    kernel's verdict on the offsets and raises."""
+    import paper_2302_08381_amd as sph
+    pts = np.random.default_rng(3).standard_normal((10, 3))
+    xyz = to_dev(pts, torch.float32)
+    with pytest.raises(sph.SphError) as ei:
+        sph.sph_batched_compute(xyz, _offsets(np.array([0, 6, 4, 10])), 3, True)
+    assert ei.value.status == 4
+    R = to_dev(standard_normal((10, 4, 2), 4), torch.float32)
+    with pytest.raises(sph.SphError):
+        sph.sph_radial_expansion(xyz, _offsets(np.array([0, 3, 11])), R, 3, True)
+    G = to_dev(standard_normal((2, 2, 16), 5), torch.float32)
+    with pytest.raises(sph.SphError):
+        sph.sph_radial_expansion_backward(xyz, _offsets(np.array([1, 3, 10])), R, G, 3, True)
+    # consistent offsets pass, and check=False leaves the call unchecked
+    sph.sph_batched_compute(xyz, _offsets(np.array([0, 4, 10])), 3, True)
+    sph.sph_batched_compute(xyz, _offsets(np.array([0, 6, 4, 10])), 3, True, check=False)
+    torch.cuda.synchronize()
 
 
 @pytest.mark.parametrize("l_max", [3, 8, 12])
