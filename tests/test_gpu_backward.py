@@ -43,6 +43,36 @@ def test_backward_matches_oracle(l_max, dtype):
     assert err.max() <= TOL[dtype], err.max()
 
 
+@pytest.mark.parametrize("dtype,l_max", [(torch.float64, 8), (torch.float32, 4), (torch.float32, 6)])
+def test_backward_resident_grid_full_size(dtype, l_max):
+    """N = 1e6 (the plain GPU-sized workload's points): far more tiles than
+    the resident grid holds, so every block runs the loop that loads tile
+    t + G while it reduces tile t.  Compared with the oracle on 2048 rows
+    that include each of the last tiles of the run, where the loop ends."""
+    import paper_2302_08381_amd as sph
+    n = 1_000_000
+    print(f"backward resident grid {dtype} l_max={l_max} n={n}", flush=True)
+    pts = standard_normal_points(n, SEEDS["plain_gpu"])
+    K = (l_max + 1) ** 2
+    xyz = to_dev(pts, dtype)
+    gY = to_dev(standard_normal((n, K), SEEDS["plain_gpu_grad"]), dtype)
+    _, dY = sph.sph_compute_with_gradients(xyz, l_max, True)
+    gx = sph.sph_backward(dY, gY, l_max)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(17)
+    # 1536 random rows plus the last 512 rows (the final tiles and the
+    # ragged end of every block's walk)
+    idx = np.unique(np.concatenate([rng.choice(n - 512, 1536, replace=False), np.arange(n - 512, n)]))
+    ii = torch.as_tensor(idx, device="cuda")
+    hp = host_points(xyz[ii])
+    _, Gr = oracle.real_sph(hp, l_max, True)
+    gYh = gY[ii].cpu().double().numpy()
+    err = _rel_err_vec(gx[ii].cpu().numpy(), oracle.backward(Gr, gYh), _contraction_scale(gYh, hp, l_max, True))
+    assert err.max() <= TOL[dtype], err.max()
+    # every row written and finite
+    assert np.isfinite(gx.cpu().numpy()).all()
+
+
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 @pytest.mark.parametrize("normalize", [False, True])
 @pytest.mark.parametrize("l_max", [0, 1, 2, 3, 4, 6, 8, 9])
@@ -150,11 +180,14 @@ def test_differentiation_workload_finite_differences():
     _, g, hs = oracle.component_scales(hp, L, True)
     gYh = gY64.cpu().numpy()
     sb = (np.abs(gYh) * g).sum(1)[:, None]
-    # FD truncation ~ h^2 |d3|: accept 1e-5 of the scale
-    assert (_rel_err_vec(gx[ii].double().cpu().numpy(), fd_b.cpu().numpy(), sb)).max() < 1e-4
+    # FD truncation ~ h^2 |d3| / 6: on this sample (r >= 0.64) it is 4.2e-7 of
+    # the scale for the backward and 3.9e-7 for the double backward (the
+    # oracle's own central differences), and the float32 kernels add < 1e-6,
+    # so 1e-5 of the scale is the bound.
+    assert (_rel_err_vec(gx[ii].double().cpu().numpy(), fd_b.cpu().numpy(), sb)).max() < 1e-5
     vn = np.sqrt((v64.cpu().numpy() ** 2).sum(1))[:, None]
     sdb = (np.abs(gYh) * hs).sum(1)[:, None] * vn
-    assert (_rel_err_vec(g2[ii].double().cpu().numpy(), fd_db.cpu().numpy(), sdb)).max() < 1e-4
+    assert (_rel_err_vec(g2[ii].double().cpu().numpy(), fd_db.cpu().numpy(), sdb)).max() < 1e-5
     # against the oracle (float32 tolerance)
     _, Gr = oracle.real_sph(hp, L, True)
     assert (_rel_err_vec(gx[ii].cpu().numpy(), oracle.backward(Gr, gYh), sb)).max() <= TOL[torch.float32]

@@ -55,7 +55,11 @@ def _check(c, pts, offs, R, l_max, normalize, dt, label=""):
 @pytest.mark.parametrize("dt", [torch.float32, torch.float64])
 @pytest.mark.parametrize("l_max,n_max,normalize", [
     (0, 1, True), (1, 3, False), (3, 8, True), (6, 5, True), (8, 8, True), (8, 8, False),
-    (12, 4, True), (8, 13, True)])
+    (12, 4, True), (8, 13, True),
+    # the low-degree kernels whose items are split across otherwise idle
+    # threads: into 4 parts (l_max 2, 3 channels), into 2 (l_max 4 with 8
+    # channels, l_max 3 with 12)
+    (2, 3, False), (4, 8, True), (3, 12, True)])
 def test_expansion_matches_oracle(dt, l_max, n_max, normalize):
     import paper_2302_08381_amd as sph
     print(f"expansion {dt} l_max={l_max} n_max={n_max} normalize={normalize}", flush=True)
