@@ -112,7 +112,7 @@ def summarize(outdir: str) -> None:
         stats = list(csv.DictReader(f))
     lines = ["# Kernel trace: forward (Y+dY) and backward, l_max = 8, float32, N = 1,000,000", "",
              "Command (from /tmp, TMPDIR=/tmp):", "", "    " + cmds["trace"], "",
-             f"Kernel sources hash: {kernel_hash()}", "",
+            f"Kernel sources hash: {kernel_hash()}", "",
              "| kernel | calls | mean us | min us | max us | share % | algorithmic GB/s at mean |",
              "|---|---|---|---|---|---|---|"]
     for r in stats:
@@ -173,44 +173,135 @@ def summarize(outdir: str) -> None:
     print("\n".join(lines + [""] + md))
 
 
-def cpu_baseline(gpu_rows, n_sample: int = 200_000, chunk: int = 20_000, rows: int = 2048):
-    """The oracle (longdouble, single thread) on the first n_sample points of
-    the same workload: forward with gradients plus the backward contraction,
-    timed.  The oracle's results for `rows` random rows of the first chunk
-    also check the GPU's outputs for those rows: gpu_rows(idx) returns the
-    GPU's (Y, dY, grad_xyz) rows idx as host arrays."""
+# ------------------------------------------------------------ host oracle
+def host_cores() -> int:
+    """Worker processes for the oracle: the CPUs this process may run on,
+    at most 16 (one GPU's share of a host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_fwd_bwd(args):
+    """One chunk of the headline step on the host: the oracle's harmonics and
+    gradients, then its backward contraction (a pool worker)."""
+    import oracle
+    pts, gY = args
+    _, G = oracle.real_sph(pts, L_MAX, NORMALIZE)
+    oracle.backward(G, gY)
+    return pts.shape[0]
+
+
+def _per_l(gpu, ref, pts, l_max, normalize, kind):
+    import oracle
+    mx, rms = oracle.per_l_errors(gpu, ref, pts, l_max, normalize, kind)
+    return {"max": [float(v) for v in mx], "rms": [float(v) for v in rms]}
+
+
+def _contraction_err(gx, ref, gY, pts, l_max, normalize):
+    """max and RMS of |grad_xyz - ref| / sum_k |gY_k| g_l(k)."""
+    import numpy as np
+
+    import oracle
+    _, g, _ = oracle.component_scales(pts, l_max, normalize)
+    e = np.abs(np.asarray(gx, float) - np.asarray(ref, float)) / (np.abs(gY) * g).sum(1)[:, None]
+    return {"max": float(e.max()), "rms": float(np.sqrt((e ** 2).mean()))}
+
+
+def cpu_baseline(pool, gpu_rows, gpu_rows_f64, gpu_c1, n_single: int = 200_000, chunk: int = 20_000):
+    """The oracle (numpy longdouble recurrence tier) on the host:
+
+    * all cores: the whole headline workload (1e6 points, forward with
+      gradients and the backward contraction) over the worker pool;
+    * one thread: its first n_single points, for comparison;
+    * the CPU-sized workload (N = 1000, float64, l_max = 4, both kinds) in
+      full, whose results also check the GPU's.
+
+    The oracle's results for the first chunk (20 000 rows) check the GPU's
+    rows at float32 and float64: per-l max and RMS of the scaled errors of Y
+    and dY, and of grad_xyz.  gpu_rows(n) / gpu_rows_f64(n) return the GPU's
+    (Y, dY, grad_xyz) for the first n rows as host arrays; gpu_c1(normalize)
+    the GPU's (Y, dY) of the CPU-sized workload."""
     import numpy as np
 
     import oracle
     from workloads import SEEDS, standard_normal, standard_normal_points
 
-    pts = standard_normal_points(N_POINTS, SEEDS["plain_gpu"])[:n_sample].astype(np.float32)
     K = (L_MAX + 1) ** 2
-    gY = standard_normal((N_POINTS, K), SEEDS["plain_gpu_grad"])[:n_sample].astype(np.float32)
-    idx = np.sort(np.random.default_rng(7).choice(min(chunk, n_sample), rows, replace=False))
+    pts64 = standard_normal_points(N_POINTS, SEEDS["plain_gpu"])
+    gY64 = standard_normal((N_POINTS, K), SEEDS["plain_gpu_grad"])
+    pts = pts64.astype(np.float32)
+    gY = gY64.astype(np.float32)
+
+    # all cores, the whole workload
+    cores = pool._processes
+    t0 = time.perf_counter()
+    done = sum(pool.imap_unordered(_oracle_fwd_bwd, ((pts[s:s + chunk], gY[s:s + chunk])
+                                                     for s in range(0, N_POINTS, chunk))))
+    t_all = time.perf_counter() - t0
+    assert done == N_POINTS
+
+    # one thread, the first n_single points; the first chunk's results kept
     kept = None
     t0 = time.perf_counter()
-    for s in range(0, n_sample, chunk):
+    for s in range(0, n_single, chunk):
         Yr, G = oracle.real_sph(pts[s:s + chunk], L_MAX, NORMALIZE)
         gr = oracle.backward(G, gY[s:s + chunk])
         if s == 0:
-            kept = (Yr[idx], G[idx], gr[idx])
-    dt = time.perf_counter() - t0
+            kept = (Yr, G, gr)
+    t_one = time.perf_counter() - t0
 
-    # the GPU's rows against the oracle's (inputs: the same float32 values)
-    Yg, dYg, gxg = gpu_rows(idx)
-    hp = pts[idx].astype(np.float64)
-    my, _ = oracle.per_l_errors(Yg, kept[0], hp, L_MAX, NORMALIZE, "Y")
-    md, _ = oracle.per_l_errors(dYg, kept[1], hp, L_MAX, NORMALIZE, "dY")
-    _, g, _ = oracle.component_scales(hp, L_MAX, NORMALIZE)
-    gYh = gY[idx].astype(np.float64)
-    mb = float((np.abs(gxg - np.asarray(kept[2], float)) / (np.abs(gYh) * g).sum(1)[:, None]).max())
-    acc = {"rows_checked": rows, "rows": f"{rows} random rows of the first {chunk}",
-           "Y_max_scaled_err": float(my.max()), "dY_max_scaled_err": float(md.max()),
-           "grad_xyz_max_scaled_err": mb, "tolerance": 1e-5}
-    return {"value": n_sample / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n_sample} of the {N_POINTS} points, Y+dY and backward, "
-                      f"numpy longdouble recurrence tier, {dt:.1f} s wall, 1 thread"}, acc
+    # the GPU's first chunk against the oracle's, float32 (the oracle sees
+    # the same rounded inputs) and float64
+    acc = {"rows": f"the first {chunk} rows of the {N_POINTS}-point workload",
+           "metric": "per-l max and RMS of |gpu - oracle| / s_l (values) or g_l (gradients), the addition-"
+                     "theorem scales; grad_xyz: |gpu - oracle| / sum_k |grad_Y_k| g_l(k)",
+           "tolerance": {"f32": 1e-5, "f64": 1e-12}}
+    hp = pts[:chunk].astype(np.float64)
+    Yg, dYg, gxg = gpu_rows(chunk)
+    acc["f32"] = {"Y": _per_l(Yg, kept[0], hp, L_MAX, NORMALIZE, "Y"),
+                  "dY": _per_l(dYg, kept[1], hp, L_MAX, NORMALIZE, "dY"),
+                  "grad_xyz": _contraction_err(gxg, kept[2], gY[:chunk].astype(np.float64), hp, L_MAX, NORMALIZE)}
+    Yr, G = oracle.real_sph(pts64[:chunk], L_MAX, NORMALIZE)
+    gr = oracle.backward(G, gY64[:chunk])
+    Yg, dYg, gxg = gpu_rows_f64(chunk)
+    acc["f64"] = {"Y": _per_l(Yg, Yr, pts64[:chunk], L_MAX, NORMALIZE, "Y"),
+                  "dY": _per_l(dYg, G, pts64[:chunk], L_MAX, NORMALIZE, "dY"),
+                  "grad_xyz": _contraction_err(gxg, gr, gY64[:chunk], pts64[:chunk], L_MAX, NORMALIZE)}
+
+    # the CPU-sized workload in full: N = 1000, float64, l_max = 4
+    p1 = standard_normal_points(1000, SEEDS["plain_cpu"])
+    c1 = {}
+    for norm in (False, True):
+        t0 = time.perf_counter()
+        Yr, G = oracle.real_sph(p1, 4, norm)
+        dt = time.perf_counter() - t0
+        Yg, dYg = gpu_c1(norm)
+        c1[f"normalize={int(norm)}"] = {"oracle_s": dt, "oracle_ns_per_point": dt / 1000 * 1e9,
+                                        "Y": _per_l(Yg, Yr, p1, 4, norm, "Y"),
+                                        "dY": _per_l(dYg, G, p1, 4, norm, "dY")}
+    acc["plain_cpu_sized_f64_l4"] = c1
+
+    base = {"value": N_POINTS / t_all, "unit": "points/s", "cores": cores, "kind": "oracle",
+            "sample": f"the whole workload ({N_POINTS} points, Y+dY and backward), numpy longdouble recurrence "
+                      f"tier, {t_all:.1f} s wall on {cores} worker processes (one thread each)",
+            "host": {"cpu_model": cpu_model(), "os_cpu_count": os.cpu_count(), "workers": cores},
+            "one_thread": {"value": n_single / t_one, "unit": "points/s",
+                           "sample": f"first {n_single} points, {t_one:.1f} s wall, 1 thread"}}
+    return base, acc
 
 
 def _time(fn, reps: int, warm: int = 3) -> float:
@@ -304,7 +395,8 @@ def extras(dev):
         gYc = torch.as_tensor(standard_normal((nb, Kb), 1000 + Lb), dtype=torch.float32).to(dev)
         o = {"Y": torch.empty((nb, Kb), device=dev), "dY": torch.empty((nb, 3, Kb), device=dev),
              "grad_xyz": torch.empty((nb, 3), device=dev)}
-        tbat = _time(lambda: sph.sph_batched_compute(xc, oc, Lb, True, store_dY=True, grad_Y=gYc, out=o), 20)
+        tbat = _time(lambda: sph.sph_batched_compute(xc, oc, Lb, True, store_dY=True, grad_Y=gYc, out=o,
+                                                          check=False), 20)
         Yp = torch.empty((nb, Kb), device=dev)
         dYp = torch.empty((nb, 3, Kb), device=dev)
         gxp = torch.empty((nb, 3), device=dev)
@@ -328,7 +420,7 @@ def extras(dev):
         Kb = (Lb + 1) ** 2
         Rc = torch.as_tensor(gaussian_radial_basis(pts, Lb, NMX, 5.0), dtype=torch.float32).to(dev)
         cc = torch.empty((offs.size - 1, NMX, Kb), device=dev)
-        tex = _time(lambda: sph.sph_radial_expansion(xc, oc, Rc, Lb, True, out=cc), 20)
+        tex = _time(lambda: sph.sph_radial_expansion(xc, oc, Rc, Lb, True, out=cc, check=False), 20)
         lk = torch.tensor([l for l in range(Lb + 1) for _ in range(2 * l + 1)], device=dev)
         Yu = torch.empty((nb, Kb), device=dev)
         acc = torch.empty((offs.size - 1, Kb, NMX), device=dev)
@@ -340,7 +432,7 @@ def extras(dev):
         tun = _time(unfused, 5)
         byts = nb * 4 * (3 + (Lb + 1) * NMX) + (offs.size - 1) * (8 + 4 * NMX * Kb)
         Gc = torch.as_tensor(standard_normal((offs.size - 1, NMX, Kb), 700 + Lb), dtype=torch.float32).to(dev)
-        tbw = _time(lambda: sph.sph_radial_expansion_backward(xc, oc, Rc, Gc, Lb, True), 10)
+        tbw = _time(lambda: sph.sph_radial_expansion_backward(xc, oc, Rc, Gc, Lb, True, check=False), 10)
         exp[str(Lb)] = {"fused_s": tex, "unfused_s": tun, "backward_s": tbw, "points": nb, "n_max": NMX,
                         "fused_points_per_s": nb / tex, "fused_GB_per_s": byts / tex / 1e9,
                         "backward_points_per_s": nb / tbw}
@@ -355,12 +447,107 @@ def extras(dev):
         row = {}
         for variant in ("default", "runtime_degree"):
             sph.sph_batched_set_config(Ls, True, torch.float32, True, False, variant, 0)
-            row[variant + "_s"] = _time(lambda: sph.sph_batched_compute(xc, oc, Ls, True, store_dY=True, out=o), 20)
+            row[variant + "_s"] = _time(lambda: sph.sph_batched_compute(xc, oc, Ls, True, store_dY=True, out=o,
+                                                                              check=False), 20)
         row["GB_per_s_default"] = nb * 4 * (3 + 4 * Ks) / row["default_s"] / 1e9
         sph.sph_batched_set_config(Ls, True, torch.float32, True, False, "default", 0)
         spec[str(Ls)] = row
     out["compile_time_vs_runtime_degree_f32"] = spec
     return out
+
+
+# ------------------------------------------------------------ precision report
+PRECISION_COMMAND = "python3 bench.py --precision-report gpurun_out/precision_l32.md"
+PRECISION_CLASSES = ("unit sphere", "near the poles", "radii 1e-6..1e3")
+
+
+def _precision_chunk(args):
+    """Per class: (points, Y max[l], Y rms[l], dY max[l], dY rms[l]) of one
+    chunk of GPU rows against the oracle (a pool worker)."""
+    import oracle
+    pts, Yg, dYg, cls = args
+    Yr, G = oracle.real_sph(pts, 32, True)
+    out = {}
+    for c in range(len(PRECISION_CLASSES)):
+        m = cls == c
+        if m.any():
+            my, ry = oracle.per_l_errors(Yg, Yr, pts, 32, True, "Y", mask=m)
+            md, rd = oracle.per_l_errors(dYg, G, pts, 32, True, "dY", mask=m)
+            out[c] = (int(m.sum()), my, ry, md, rd)
+    return out
+
+
+def precision_report(dev, pool, path: str, per_class: int = 20_000, chunk: int = 1000) -> None:
+    """Per-l max and RMS of the scaled errors of Y and dY against the oracle
+    on the l_max = 32 stress workload (N = 200 000, normalised), float32 and
+    float64, per sub-population: the GPU computes all 200 000 points in one
+    call; per_class points of each class are checked."""
+    import numpy as np
+    import torch
+
+    import paper_2302_08381_amd as sph
+    from workloads import SEEDS, precision_stress_points
+
+    L = 32
+    pts, cls = precision_stress_points(200_000, SEEDS["precision"])
+    rng = np.random.default_rng(55)
+    idx = np.sort(np.concatenate([rng.choice(np.flatnonzero(cls == c), per_class, replace=False)
+                                  for c in range(len(PRECISION_CLASSES))]))
+    ii = torch.as_tensor(idx, device=dev)
+    head = ["# Per-l accuracy at l_max = 32: the precision stress workload", "",
+            "Command (repository root, one GPU):", "", "    " + PRECISION_COMMAND, "",
+            f"Kernel sources hash: {kernel_hash()}", "",
+            f"Workload: N = 200 000 points, normalised harmonics, l_max = 32 (K = 1089): 100 000 on the unit "
+            f"sphere, 50 000 with |x|, |y| ~ 10^U(-12,-3) and z = +-1, 50 000 isotropic with r ~ 10^U(-6,3) "
+            f"(seed {SEEDS['precision']}).  The GPU computes Y and dY for all 200 000 points in one call; "
+            f"{per_class} points of each class (seeded choice) are compared with the oracle (numpy longdouble "
+            f"recurrence tier) on the inputs the kernel saw (float32-rounded for the float32 run).", "",
+            "Error: |gpu - oracle| / s_l for values and / g_l for gradients, with the addition-theorem scales "
+            "s_l = sqrt((2l+1)/4pi) and g_l = sqrt(l(l+1)(2l+1)/4pi)/r; max and RMS over the class's points, "
+            "the 2l+1 orders and (for dY) the three axes.  Tolerances: float32 1e-5, float64 1e-12.", ""]
+    summary, tables = [], []
+    for dt, name in ((torch.float32, "float32"), (torch.float64, "float64")):
+        x = torch.as_tensor(pts, dtype=dt).to(dev)
+        Y, dY = sph.sph_compute_with_gradients(x, L, True)
+        ph = x[ii].double().cpu().numpy()
+        Yh = Y[ii].double().cpu().numpy()
+        dYh = dY[ii].double().cpu().numpy()
+        del x, Y, dY
+        torch.cuda.empty_cache()
+        ch = cls[idx]
+        nc = len(PRECISION_CLASSES)
+        ymax = np.zeros((nc, L + 1))
+        dmax = np.zeros((nc, L + 1))
+        ysq = np.zeros((nc, L + 1))
+        dsq = np.zeros((nc, L + 1))
+        npts = np.zeros(nc, np.int64)
+        ls = np.arange(L + 1)
+        jobs = ((ph[s:s + chunk], Yh[s:s + chunk], dYh[s:s + chunk], ch[s:s + chunk])
+                for s in range(0, idx.size, chunk))
+        for res in pool.imap_unordered(_precision_chunk, jobs):
+            for c, (n, my, ry, md, rd) in res.items():
+                npts[c] += n
+                ymax[c] = np.maximum(ymax[c], my)
+                dmax[c] = np.maximum(dmax[c], md)
+                ysq[c] += ry ** 2 * n * (2 * ls + 1)
+                dsq[c] += rd ** 2 * n * 3 * (2 * ls + 1)
+        for c, cname in enumerate(PRECISION_CLASSES):
+            yr = np.sqrt(ysq[c] / (npts[c] * (2 * ls + 1)))
+            dr = np.sqrt(dsq[c] / (npts[c] * 3 * (2 * ls + 1)))
+            summary.append(f"| {name} | {cname} | {npts[c]} | {ymax[c].max():.2e} | {dmax[c].max():.2e} | "
+                           f"{yr.max():.2e} | {dr.max():.2e} |")
+            tables += [f"## {name}, {cname} ({npts[c]} points)", "",
+                       "| l | Y max | Y RMS | dY max | dY RMS |", "|---|---|---|---|---|"]
+            tables += [f"| {l} | {ymax[c, l]:.2e} | {yr[l]:.2e} | {dmax[c, l]:.2e} | {dr[l]:.2e} |"
+                       for l in range(L + 1)]
+            tables.append("")
+        print(f"precision report: {name} done", flush=True)
+    table_head = ["| dtype | class | points | Y max | dY max | Y RMS | dY RMS |", "|---|---|---|---|---|---|---|"]
+    lines = head + ["Summary (largest over l):", ""] + table_head + summary + [""] + tables
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(table_head + summary), flush=True)
 
 
 EXPANSION_PROFILE_COMMAND = ("rocprofv3 --kernel-trace --stats --output-format csv -d {out}/prof_expand -o run -- "
@@ -391,8 +578,8 @@ def profile_expansion(dev, steps: int, warmup: int) -> None:
     c = torch.empty((n_env, EXPANSION_CHANNELS, (EXPANSION_L + 1) ** 2), device=dev)
 
     def step():
-        sph.sph_radial_expansion(xyz, o, R, EXPANSION_L, True, out=c)
-        sph.sph_radial_expansion_backward(xyz, o, R, G, EXPANSION_L, True)
+        sph.sph_radial_expansion(xyz, o, R, EXPANSION_L, True, out=c, check=False)
+        sph.sph_radial_expansion_backward(xyz, o, R, G, EXPANSION_L, True, check=False)
     for _ in range(warmup + steps):
         step()
     torch.cuda.synchronize()
@@ -447,6 +634,9 @@ def main():
     ap.add_argument("--profile-expansion", action="store_true",
                     help="only run the radial expansion and its backward (l_max = 8, the 20 000 batched "
                          "environments, 8 channels, float32): warmup + steps, for rocprofv3")
+    ap.add_argument("--precision-report", metavar="PATH",
+                    help="write the per-l accuracy tables of the l_max = 32 stress workload (float32 and float64, "
+                         "per sub-population) to PATH")
     ap.add_argument("--summarize-expansion", metavar="DIR",
                     help="write profiles/expansion_l8_f32.md from the kernel trace in DIR/prof_expand (no GPU)")
     args = ap.parse_args()
@@ -462,6 +652,13 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    # The oracle's worker processes are forked before anything touches the
+    # GPU, so they hold no device state.
+    pool = None
+    if args.precision_report or not (args.no_cpu_baseline or args.profile or args.profile_expansion):
+        import multiprocessing as mp
+        pool = mp.get_context("fork").Pool(host_cores())
+
     import torch
 
     import paper_2302_08381_amd as sph
@@ -471,6 +668,11 @@ def main():
     torch.cuda.set_device(dev)
     if args.profile_expansion:
         profile_expansion(dev, args.steps, args.warmup)
+        return
+    if args.precision_report:
+        precision_report(dev, pool, args.precision_report)
+        pool.close()
+        pool.join()
         return
     K = (L_MAX + 1) ** 2
     xyz = torch.as_tensor(standard_normal_points(N_POINTS, SEEDS["plain_gpu"]), dtype=torch.float32).to(dev)
@@ -576,12 +778,26 @@ def main():
     }
     if not args.no_extras:
         out["extra"] = extras(dev)
-    if not args.no_cpu_baseline:
-        def gpu_rows(idx):
-            ii = torch.as_tensor(idx, device=dev)
-            return (Y[ii].double().cpu().numpy(), dY[ii].double().cpu().numpy(),
-                    gx[ii].double().cpu().numpy())
-        out["cpu_baseline"], out["accuracy"] = cpu_baseline(gpu_rows)
+    if pool is not None:
+        def gpu_rows(n):
+            return Y[:n].double().cpu().numpy(), dY[:n].double().cpu().numpy(), gx[:n].double().cpu().numpy()
+
+        def gpu_rows_f64(n):
+            # the float64 run of the same workload, whole, sliced
+            x64 = torch.as_tensor(standard_normal_points(N_POINTS, SEEDS["plain_gpu"]), dtype=torch.float64).to(dev)
+            g64 = torch.as_tensor(standard_normal((N_POINTS, K), SEEDS["plain_gpu_grad"]),
+                                  dtype=torch.float64).to(dev)
+            Y64, dY64 = sph.sph_compute_with_gradients(x64, L_MAX, NORMALIZE)
+            gx64 = sph.sph_backward(dY64, g64, L_MAX)
+            return Y64[:n].cpu().numpy(), dY64[:n].cpu().numpy(), gx64[:n].cpu().numpy()
+
+        def gpu_c1(norm):
+            x1 = torch.as_tensor(standard_normal_points(1000, SEEDS["plain_cpu"]), dtype=torch.float64).to(dev)
+            Y1, dY1 = sph.sph_compute_with_gradients(x1, 4, norm)
+            return Y1.cpu().numpy(), dY1.cpu().numpy()
+        out["cpu_baseline"], out["accuracy"] = cpu_baseline(pool, gpu_rows, gpu_rows_f64, gpu_c1)
+        pool.close()
+        pool.join()
     print(json.dumps(out), flush=True)
 
 
