@@ -140,6 +140,23 @@ int32_t sph_double_backward(const void* xyz, const void* grad_Y, const void* v,
                             void* stream);
 
 /*
+ * sph_compute_with_hessians -- Y[n,K], dY[n,3,K] and the second derivatives
+ * d2Y[n,3,3,K], d2Y[i,a,b,k] = d^2 Y[i,k] / (d xyz[i,a] d xyz[i,b]) (the full
+ * symmetric 3x3 block of every column).  Sec. II: the Cartesian recursion
+ * gives derivatives of any order; here Eq. iter-deri is applied twice, with
+ * the product rule and, for normalize = 1, the chain rule through x/r
+ * (Sec. III).  At r = 0 the normalised second derivatives are 0.
+ *   Y          out [n,K]       (required)
+ *   dY         out [n,3,K]     (may be NULL: not stored)
+ *   d2Y        out [n,3,3,K]   (required)
+ * Other arguments as sph_compute.  Two launches on `stream`: the forward of
+ * sph_compute_with_gradients, then the second-derivative kernel.
+ */
+int32_t sph_compute_with_hessians(const void* xyz, int64_t n, int32_t l_max,
+                                  int32_t normalize, int32_t dtype, void* Y,
+                                  void* dY, void* d2Y, void* stream);
+
+/*
  * sph_batched_compute -- many neighbour lists in one persistent launch.
  * The points of n_env environments are concatenated (CSR): environment e
  * owns rows offsets[e] .. offsets[e+1]-1 of xyz (Sec. III: the harmonics of
@@ -222,9 +239,7 @@ int32_t sph_radial_expansion(const void* xyz, const int64_t* offsets, int64_t n_
  *   grad_xyz   out [n_points, 3]              (may be NULL)
  *   grad_R     out [n_points, l_max+1, n_max] (may be NULL)
  * Rows of points outside every environment's range (possible only with
- * inconsistent offsets) are not written.  SPH_ERR_INVALID if the block's
- * LDS (the environment's grad_c and one row per thread) would exceed
- * 160 KiB (double l_max >= 28 with more than 8 channels).
+ * inconsistent offsets) are not written.
  */
 int32_t sph_radial_expansion_backward(const void* xyz, const int64_t* offsets, int64_t n_env,
                                       int64_t n_points, const void* R, int32_t n_max,

@@ -25,6 +25,7 @@ from ._native import (  # noqa: F401
     sph_batched_set_options,
     sph_compute,
     sph_compute_with_gradients,
+    sph_compute_with_hessians,
     sph_double_backward,
     sph_radial_expansion,
     sph_radial_expansion_backward,

@@ -42,6 +42,7 @@ _SIGNATURES = {
     "sph_version": (ctypes.c_char_p, []),
     "sph_compute": (_i32, [_vp, _i64, _i32, _i32, _i32, _vp, _vp]),
     "sph_compute_with_gradients": (_i32, [_vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp]),
+    "sph_compute_with_hessians": (_i32, [_vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp, _vp]),
     "sph_backward": (_i32, [_vp, _vp, _i64, _i32, _i32, _vp, _vp]),
     "sph_double_backward": (_i32, [_vp, _vp, _vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp]),
     "sph_batched_compute": (_i32, [_vp, _vp, _i64, _i64, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -198,6 +199,34 @@ def sph_compute_with_gradients(xyz: torch.Tensor, l_max: int, normalize: bool = 
         _check(lib().sph_compute_with_gradients(_ptr(xyz), n, int(l_max), int(bool(normalize)),
                                                 _dtype_code(xyz), _ptr(Y), _ptr(dY), _stream(xyz.device)))
     return Y, dY
+
+
+def sph_compute_with_hessians(xyz: torch.Tensor, l_max: int, normalize: bool = True,
+                              Y: torch.Tensor | None = None, dY: torch.Tensor | None = None,
+                              d2Y: torch.Tensor | None = None, store_dY: bool = True):
+    """(Y[n,K], dY[n,3,K] or None, d2Y[n,3,3,K]) (include/sph.h: sph_compute_with_hessians).
+    With ``store_dY=False`` (and no ``dY`` given) the first derivatives are
+    not stored."""
+    _check_xyz(xyz)
+    n = xyz.shape[0]
+    K = (int(l_max) + 1) ** 2 if l_max >= 0 else 0
+    if Y is None:
+        Y = torch.empty((n, K), dtype=xyz.dtype, device=xyz.device)
+    else:
+        _need(Y, "Y", (n, K), xyz.dtype, xyz.device)
+    if dY is None:
+        if store_dY:
+            dY = torch.empty((n, 3, K), dtype=xyz.dtype, device=xyz.device)
+    else:
+        _need(dY, "dY", (n, 3, K), xyz.dtype, xyz.device)
+    if d2Y is None:
+        d2Y = torch.empty((n, 3, 3, K), dtype=xyz.dtype, device=xyz.device)
+    else:
+        _need(d2Y, "d2Y", (n, 3, 3, K), xyz.dtype, xyz.device)
+    with torch.cuda.device(xyz.device):
+        _check(lib().sph_compute_with_hessians(_ptr(xyz), n, int(l_max), int(bool(normalize)), _dtype_code(xyz),
+                                               _ptr(Y), _ptr(dY), _ptr(d2Y), _stream(xyz.device)))
+    return Y, dY, d2Y
 
 
 def sph_backward(dY: torch.Tensor, grad_Y: torch.Tensor, l_max: int, grad_xyz: torch.Tensor | None = None):

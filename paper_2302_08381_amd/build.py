@@ -44,6 +44,8 @@ SOURCES = [
     "sph_kernels_bwd_f64.hip",
     "sph_kernels_expand_f32.hip",
     "sph_kernels_expand_f64.hip",
+    "sph_kernels_hess_f32.hip",
+    "sph_kernels_hess_f64.hip",
     "sph_api.cpp",
 ]
 COMMON = [

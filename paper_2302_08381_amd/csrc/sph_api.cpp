@@ -417,6 +417,38 @@ int32_t sph_double_backward(const void* xyz, const void* grad_Y, const void* v, 
   return ok();
 }
 
+int32_t sph_compute_with_hessians(const void* xyz, int64_t n, int32_t l_max, int32_t normalize, int32_t dtype,
+                                  void* Y, void* dY, void* d2Y, void* stream) {
+  int32_t st = check_common(n, l_max, dtype);
+  if (st != SPH_OK) return st;
+  if ((st = check_norm(normalize)) != SPH_OK) return st;
+  if (n == 0) return ok();
+  if (xyz == nullptr || Y == nullptr || d2Y == nullptr) return fail(SPH_ERR_NULL, "xyz, Y and d2Y are required");
+  const size_t w = elem_size(dtype);
+  const size_t K = static_cast<size_t>(sph_num_components(l_max));
+  const size_t un = static_cast<size_t>(n);
+  if ((st = check_no_overlap({{Y, un * K * w, "Y"}, {dY, un * 3 * K * w, "dY"}, {d2Y, un * 9 * K * w, "d2Y"}},
+                             {{xyz, un * 3 * w, "xyz"}, {Y, un * K * w, "Y"}, {dY, un * 3 * K * w, "dY"},
+                              {d2Y, un * 9 * K * w, "d2Y"}})) != SPH_OK)
+    return st;
+  const sph::KernelInfo kf = fwd_info(dtype, l_max, normalize, dY != nullptr, false);
+  const sph::KernelInfo kh = dtype == SPH_F64 ? sph::hess_info_f64(l_max, normalize)
+                                              : sph::hess_info_f32(l_max, normalize);
+  if (kf.fn == nullptr || kh.fn == nullptr) return fail(SPH_ERR_INVALID, "no kernel for these arguments");
+  hipError_t e = ensure_lds(kf.fn, kf.lds_bytes);
+  if (e == hipSuccess) e = ensure_lds(kh.fn, kh.lds_bytes);
+  if (e != hipSuccess) return device_fail(e, "hipFuncSetAttribute");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // values and first derivatives: the forward kernel of sph_compute_with_gradients
+  sph::FwdParams pf{xyz, n, l_max, Y, dY, nullptr, nullptr, nullptr, 0, nullptr};
+  e = launch(kf.fn, static_cast<unsigned>(plain_grid(ceil_div(n, kf.tile_points))), kf.block, kf.lds_bytes, &pf, s);
+  if (e != hipSuccess) return device_fail(e, "forward launch");
+  sph::HessParams ph{xyz, n, l_max, d2Y};
+  e = launch(kh.fn, static_cast<unsigned>(plain_grid(ceil_div(n, kh.tile_points))), kh.block, kh.lds_bytes, &ph, s);
+  if (e != hipSuccess) return device_fail(e, "hessian launch");
+  return ok();
+}
+
 int32_t sph_radial_expansion(const void* xyz, const int64_t* offsets, int64_t n_env, int64_t n_points,
                              const void* R, int32_t n_max, int32_t l_max, int32_t normalize, int32_t dtype,
                              void* c, int32_t* status, void* stream) {
@@ -493,8 +525,11 @@ int32_t sph_radial_expansion_backward(const void* xyz, const int64_t* offsets, i
   hipError_t e = ensure_lds(ki.fn, ki.lds_bytes);
   if (e != hipSuccess) return device_fail(e, "hipFuncSetAttribute");
   sph::ExpandBwdParams p{xyz, R, offsets, n_env, n_points, l_max, n_max, grad_c, grad_xyz, grad_R, status};
+  // a resident grid of one-wave blocks, each block's lane groups
+  // (tile_points of them) walking their own environments
   const int64_t resident = static_cast<int64_t>(num_cus()) * resident_per_cu(ki.fn, ki.block, ki.lds_bytes);
-  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(n_env, std::max<int64_t>(resident, 1)));
+  const int64_t grid =
+      std::max<int64_t>(1, std::min<int64_t>(ceil_div(n_env, ki.tile_points), std::max<int64_t>(resident, 1)));
   e = launch(ki.fn, static_cast<unsigned>(grid), ki.block, ki.lds_bytes, &p, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return device_fail(e, "radial expansion backward launch");
   return ok();

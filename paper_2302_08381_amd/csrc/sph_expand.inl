@@ -6,7 +6,7 @@
 // environment at a time, writes the values of a chunk of its points into an
 // LDS tile, copies the chunk's radial values next to it, and contracts the
 // two tiles into per-thread accumulators; partial sums of environments
-// longer than one chunk wait in LDS.  Backward: one thread per point, see
+// longer than one chunk wait in LDS.  Backward: one lane per point, see
 // k_expand_bwd.
 #pragma once
 
@@ -300,110 +300,395 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandParams P) {
   }
 }
 
+// One point of the expansion backward: grad_R of every degree and grad_xyz.
+// The point's radial values come from one of three sources:
+//   SRC = 0: its row in an LDS tile, [degree][NPC channels] (zero padded);
+//            grad_R goes back into the same slots, degree by degree, after
+//            they are read;
+//   SRC = 1: global memory as 16-byte vectors (channels = NPC, 16-byte
+//            aligned), in one of two register buffers, the next degree's
+//            loads issued before this degree's arithmetic;
+//   SRC = 2: global memory element by element.
+template <typename T, int MM, bool NORM, int NPC, int SRC>
+__device__ __forceinline__ void expand_bwd_point(const T* __restrict__ xyz, const T* __restrict__ R,
+                                                 const T* __restrict__ sG, T* __restrict__ sRow,
+                                                 T* __restrict__ gxyz, T* __restrict__ gR, int64_t j, int L,
+                                                 int NM) {
+  using V = typename Vec16<T>::type;
+  constexpr int W = Vec16<T>::n;
+  constexpr int NV = NPC / W;
+  constexpr T kIS2 = T(kInvSqrt2d);
+  const CoefTable<T>& C = coef<T>();
+  const Point<T> pt = make_point<T, NORM>(xyz[j * 3], xyz[j * 3 + 1], xyz[j * 3 + 2]);
+  const T ex = pt.ex, ey = pt.ey, ez = pt.ez;
+  // order-m factors: c_m, s_m, m c_{m-1}, m s_{m-1} (buckets up to m = 12)
+  constexpr bool kTab = MM <= 12;
+  constexpr int MT = kTab ? MM + 1 : 1;
+  T tc[MT], ts[MT], tmc[MT], tms[MT];
+  if constexpr (kTab) {
+    T s1 = T(0), c1 = T(1), s0 = T(0), c0 = T(1);
+#pragma unroll
+    for (int m = 0; m <= MM; ++m) {
+      if (m > 0) {
+        const T sn = ex * s0 + ey * c0;
+        const T cn = ex * c0 - ey * s0;
+        s1 = s0;
+        c1 = c0;
+        s0 = sn;
+        c0 = cn;
+      }
+      tc[m] = c0;
+      ts[m] = s0;
+      tmc[m] = T(m) * c1;
+      tms[m] = T(m) * s1;
+    }
+  }
+  T prev[MM + 3], cur[MM + 3];
+#pragma unroll
+  for (int m = 0; m < MM + 3; ++m) prev[m] = T(0);
+  T g0 = T(0), g1 = T(0), g2 = T(0);
+  const T* Rj = R + j * (L + 1) * NM;
+  T* gRj = gR != nullptr ? gR + j * (L + 1) * NM : nullptr;
+  V ra[NV], rb[NV];
+  auto load_r = [&](int l, V (&dst)[NV]) {
+#pragma unroll
+    for (int h = 0; h < NV; ++h) dst[h] = __builtin_nontemporal_load(reinterpret_cast<const V*>(Rj + l * NPC) + h);
+  };
+  // degree l; SRC = 1: radial values in rc, the next degree's loads issued
+  // into rx first (unconditionally: the last degree loads itself again, so
+  // the wait analysis sees one path)
+  auto degree = [&](int l, const V (&rc)[NV], V (&rx)[NV]) {
+    if constexpr (SRC == 1) load_r(l < L ? l + 1 : l, rx);
+    q_row_rt<T, MM>(l, ez, pt.rxy2, cur);
+    T r[NPC], acc[NPC];
+    if constexpr (SRC == 0) {
+      const V* sv = reinterpret_cast<const V*>(sRow + l * NPC);
+#pragma unroll
+      for (int h = 0; h < NV; ++h) {
+        const V v = sv[h];
+#pragma unroll
+        for (int u = 0; u < W; ++u) r[h * W + u] = v[u];
+      }
+    }
+#pragma unroll
+    for (int n = 0; n < NPC; ++n) {
+      if constexpr (SRC == 1) r[n] = rc[n / W][n % W];
+      if constexpr (SRC == 2) r[n] = n < NM ? Rj[l * NM + n] : T(0);
+      acc[n] = T(0);
+    }
+    const int k0 = l * l + l;
+    // sums over the row of gY times the scaled derivatives and the value;
+    // normalised, d Y = (d Yt - l u Yt) / r, so the row adds
+    // (S_d - l u S_Y) / r once instead of normalising every column
+    T sx = T(0), sy = T(0), sz = T(0), sY = T(0);
+    // one column: value Yt and scaled derivatives (dx, dy, dz)
+    auto col = [&](int k, T Yt, T dx, T dy, T dz) {
+      const V* gv = reinterpret_cast<const V*>(sG + k * NPC);
+      T gy = T(0);
+#pragma unroll
+      for (int h = 0; h < NV; ++h) {
+        const V g = gv[h];
+#pragma unroll
+        for (int u = 0; u < W; ++u) {
+          gy += g[u] * r[h * W + u];
+          acc[h * W + u] += g[u] * Yt;
+        }
+      }
+      sx += gy * dx;
+      sy += gy * dy;
+      sz += gy * dz;
+      if constexpr (NORM) sY += gy * Yt;
+    };
+    T s1 = T(0), c1 = T(1);  // s_{m-1}, c_{m-1}
+    T s0 = T(0), c0 = T(1);  // s_m, c_m
+#pragma unroll
+    for (int m = 0; m <= MM; ++m) {
+      if (m > l) continue;  // no early exit: keeps the loop fully unrolled
+      T c, sm, mc, ms;
+      if constexpr (kTab) {
+        const int mt = kTab ? m : 0;
+        c = tc[mt];
+        sm = ts[mt];
+        mc = tmc[mt];
+        ms = tms[mt];
+      } else {
+        if (m > 0) {
+          const T sn = ex * s0 + ey * c0;
+          const T cn = ex * c0 - ey * s0;
+          s1 = s0;
+          c1 = c0;
+          s0 = sn;
+          c0 = cn;
+        }
+        c = c0;
+        sm = s0;
+        mc = T(m) * c1;
+        ms = T(m) * s1;
+      }
+      const T q = cur[m];
+      const T Tm = (m <= l - 2) ? C.gxy[l][m] * prev[m + 1] : T(0);
+      const T Cz = (m <= l - 1) ? C.gz[l][m] * prev[m] : T(0);
+      const T xt = ex * Tm, yt = ey * Tm;
+      if (m == 0) {
+        col(k0, q * kIS2, xt * kIS2, yt * kIS2, Cz * kIS2);
+      } else {
+        col(k0 + m, q * c, xt * c + q * mc, yt * c - q * ms, Cz * c);
+        col(k0 - m, q * sm, xt * sm + q * ms, yt * sm + q * mc, Cz * sm);
+      }
+    }
+    if constexpr (NORM) {
+      const T lY = T(l) * sY;
+      g0 += (sx - lY * ex) * pt.inv_r;
+      g1 += (sy - lY * ey) * pt.inv_r;
+      g2 += (sz - lY * ez) * pt.inv_r;
+    } else {
+      g0 += sx;
+      g1 += sy;
+      g2 += sz;
+    }
+    if (gRj != nullptr) {
+      if constexpr (SRC == 0) {
+        V* sv = reinterpret_cast<V*>(sRow + l * NPC);
+#pragma unroll
+        for (int h = 0; h < NV; ++h) {
+          V v;
+#pragma unroll
+          for (int u = 0; u < W; ++u) v[u] = acc[h * W + u];
+          sv[h] = v;
+        }
+      } else if constexpr (SRC == 1) {
+#pragma unroll
+        for (int h = 0; h < NV; ++h) {
+          V v;
+#pragma unroll
+          for (int u = 0; u < W; ++u) v[u] = acc[h * W + u];
+          reinterpret_cast<V*>(gRj + l * NPC)[h] = v;
+        }
+      } else {
+#pragma unroll
+        for (int n = 0; n < NPC; ++n)
+          if (n < NM) gRj[l * NM + n] = acc[n];
+      }
+    }
+    copy_row<T, MM>(MM, cur, prev);
+  };
+  if constexpr (SRC == 1) load_r(0, ra);
+  // two degrees per trip, the radial buffers alternating
+#pragma unroll 1
+  for (int l = 0; l <= L; l += 2) {
+    degree(l, ra, rb);
+    if (l + 1 <= L) degree(l + 1, rb, ra);
+  }
+  if (gxyz != nullptr) {
+    gxyz[j * 3 + 0] = g0;
+    gxyz[j * 3 + 1] = g1;
+    gxyz[j * 3 + 2] = g2;
+  }
+}
+
+// Copies of one group's radial tile between global rows [cnt][L+1][NM]
+// (contiguous from src) and LDS rows of stride RS, [L+1][NPC] each (NPC >= NM,
+// the padding channels zero).  VEC (NM == NPC, 16-byte aligned global rows):
+// 16-byte vectors, a batch of them in flight per lane; else element by
+// element.  GS lanes of the group take part (lane gl).
+template <typename T, int NPC, int GS, bool VEC>
+__device__ __forceinline__ void expand_tile_in(T* __restrict__ sR, int RS, const T* __restrict__ src, int cnt,
+                                               int L, int NM, int gl) {
+  if constexpr (VEC) {
+    using V = typename Vec16<T>::type;
+    constexpr int W = Vec16<T>::n;
+    constexpr int NB = 6;
+    const int RV = (L + 1) * NPC / W;  // vectors per row
+    const int nv = cnt * RV;
+    const V* g = reinterpret_cast<const V*>(src);
+    int p = gl / RV, c = gl - (gl / RV) * RV;
+    const int qs = GS / RV, rq = GS - qs * RV;
+    for (int i0 = gl; i0 < nv; i0 += GS * NB) {
+      V v[NB];
+      int o[NB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        o[u] = p * RS + c * W;
+        if (i0 + u * GS < nv) v[u] = __builtin_nontemporal_load(g + i0 + u * GS);
+        p += qs;
+        c += rq;
+        if (c >= RV) {
+          c -= RV;
+          ++p;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < NB; ++u)
+        if (i0 + u * GS < nv) *reinterpret_cast<V*>(sR + o[u]) = v[u];
+    }
+  } else {
+    const int row = (L + 1) * NPC;
+    for (int s = gl; s < cnt * row; s += GS) {
+      const int p = s / row, c = s - p * row;
+      const int l = c / NPC, n = c - l * NPC;
+      sR[p * RS + c] = n < NM ? src[(p * (L + 1) + l) * NM + n] : T(0);
+    }
+  }
+}
+
+template <typename T, int NPC, int GS, bool VEC>
+__device__ __forceinline__ void expand_tile_out(const T* __restrict__ sR, int RS, T* __restrict__ dst, int cnt,
+                                                int L, int NM, int gl) {
+  if constexpr (VEC) {
+    using V = typename Vec16<T>::type;
+    constexpr int W = Vec16<T>::n;
+    const int RV = (L + 1) * NPC / W;
+    const int nv = cnt * RV;
+    V* g = reinterpret_cast<V*>(dst);
+    int p = gl / RV, c = gl - (gl / RV) * RV;
+    const int qs = GS / RV, rq = GS - qs * RV;
+    for (int i = gl; i < nv; i += GS) {
+      g[i] = *reinterpret_cast<const V*>(sR + p * RS + c * W);
+      p += qs;
+      c += rq;
+      if (c >= RV) {
+        c -= RV;
+        ++p;
+      }
+    }
+  } else {
+    const int row = (L + 1) * NM;
+    for (int s = gl; s < cnt * row; s += GS) {
+      const int p = s / row, c = s - p * row;
+      const int l = c / NM, n = c - l * NM;
+      dst[s] = sR[p * RS + l * NPC + n];
+    }
+  }
+}
+
 // Backward of the expansion for an upstream gradient G = dL/dc (chain rule):
 //   grad_R[j, l, n] = sum_m G[e, n, l^2+l+m] Y_l^m(x_j)
 //   grad_xyz[j, a]  = sum_k gY[j, k] dY_k/dx_a(x_j),
 //                     gY[j, k] = sum_n G[e, n, k] R[j, l(k), n]
-// One thread per point, the environment's G in LDS ([k][channel], read as
-// 16-byte vectors, the same address for every thread).  Degree by degree the
-// thread forms the value row (grad_R and gY of the row, gY kept in its LDS
-// row) and then the three derivative rows (Eq. iter-deri), so neither Y nor
-// dY is stored.  NPC: channels padded to a multiple of 4 held in registers.
-template <typename T, int MM, int LT, bool NORM, int NPC>
-__global__ __launch_bounds__(kExpandThreads) void k_expand_bwd(ExpandBwdParams P) {
+// One lane per point; neither Y nor dY is stored.  A block is one wave split
+// into 64 / GS groups of GS lanes, each walking its own run of environments
+// (an even share of the points) in chunks of GS points, so a wave's lanes
+// stay busy across environments of any size.  Each
+// group keeps its environment's G in its own LDS slice ([k][channel], read
+// as 16-byte vectors, one address per group).  Per point, one pass per
+// degree forms every value and derivative of the row at once (Eq. iter-deri
+// with the order-m factors tabulated once per point), contracts it with G
+// and the point's radial values of that degree, and produces the degree's
+// grad_R.  STAGE: each chunk's radial rows arrive in an LDS tile by
+// coalesced 16-byte copies and its grad_R leaves the same way, so HBM sees
+// each byte once; otherwise every lane reads and writes its own rows.  NPC:
+// channels padded to a multiple of 4 (8 or 16).
+template <typename T, int MM, bool NORM, int NPC, int GS, bool STAGE>
+__global__ __launch_bounds__(kWave) void k_expand_bwd(ExpandBwdParams P) {
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int M = LT >= 0 ? LT : MM;
-  constexpr bool CT = LT >= 0;
-  using V = typename Vec16<T>::type;
   constexpr int W = Vec16<T>::n;
-  const int tid = threadIdx.x;
-  const int L = LT >= 0 ? LT : P.L;
+  constexpr int NG = kWave / GS;
+  const int lane = threadIdx.x;
+  const int grp = lane / GS, gl = lane % GS;
+  const int L = P.L;
   const int K = (L + 1) * (L + 1);
   const int NM = P.n_max;
-  const int TS = (2 * L + 1) | 1;
-  T* sG = reinterpret_cast<T*>(smem);
-  T* sT = sG + static_cast<size_t>(K) * NPC + tid * TS;  // this thread's row
+  const int RS = expand_bwd_row_stride<T>(L, NPC);
+  T* sG = reinterpret_cast<T*>(smem) +
+          static_cast<size_t>(grp) * (static_cast<size_t>(K) * NPC + (STAGE ? static_cast<size_t>(GS) * RS : 0));
+  T* sR = sG + static_cast<size_t>(K) * NPC;
   const T* xyz = static_cast<const T*>(P.xyz);
   const T* R = static_cast<const T*>(P.R);
   const T* gc = static_cast<const T*>(P.gc);
   T* gxyz = static_cast<T*>(P.gxyz);
   T* gR = static_cast<T*>(P.gR);
+  // radial rows as whole 16-byte vectors: every padded channel present and
+  // both radial arrays 16-byte aligned (uniform)
+  const bool vec = NM == NPC && aligned16(R) && (gR == nullptr || aligned16(gR));
+  (void)W;
 
-  if (P.status != nullptr && blockIdx.x == 0 && tid < kWave) {
+  if (P.status != nullptr && blockIdx.x == 0) {
     bool ok = true;
-    for (int64_t i = tid; i < P.n_env; i += kWave) ok = ok && (P.offsets[i] <= P.offsets[i + 1]);
-    if (tid == 0) ok = ok && P.offsets[0] == 0 && P.offsets[P.n_env] == P.n;
+    for (int64_t i = lane; i < P.n_env; i += kWave) ok = ok && (P.offsets[i] <= P.offsets[i + 1]);
+    if (lane == 0) ok = ok && P.offsets[0] == 0 && P.offsets[P.n_env] == P.n;
     const bool all_ok = __all(ok);
-    if (tid == 0) P.status[0] = all_ok ? 0 : 4 /* SPH_ERR_OFFSETS */;
+    if (lane == 0) P.status[0] = all_ok ? 0 : 4 /* SPH_ERR_OFFSETS */;
   }
 
-  for (int64_t e = blockIdx.x; e < P.n_env; e += gridDim.x) {
-    int64_t b, t;
-    env_range(P.offsets, e, P.n, b, t);
-    if (t == b) continue;
-    __syncthreads();  // the previous environment's G is no longer read
-    const T* ge = gc + e * NM * K;
-    for (int i = tid; i < NPC * K; i += kExpandThreads) {
-      const int n = i / K;
-      const int k = i - n * K;
-      sG[k * NPC + n] = n < NM ? ge[i] : T(0);
+  // The groups split the points evenly: group g of G takes the environments
+  // that start in points [g n / G, (g+1) n / G) (found by binary search in
+  // the offsets; every environment has one start, so each goes to exactly
+  // one group), which keeps the two groups of a wave and all waves equally
+  // busy.  Group state: environment e (up to e_end), its range [b, t), the
+  // current chunk start j0.
+  const int64_t G = static_cast<int64_t>(gridDim.x) * NG, g = static_cast<int64_t>(blockIdx.x) * NG + grp;
+  auto first_env = [&](int64_t p) {  // first e in [0, n_env] with offsets[e] >= p
+    int64_t lo = 0, hi = P.n_env;
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      if (P.offsets[mid] < p) lo = mid + 1;
+      else hi = mid;
+    }
+    return lo;
+  };
+  int64_t e = first_env(g * P.n / G);
+  const int64_t e_end = g + 1 == G ? P.n_env : first_env((g + 1) * P.n / G);
+  int64_t b = 0, t = 0, j0 = 0;
+  auto next_env = [&]() {  // the group's next non-empty environment at or after e
+    for (; e < e_end; ++e) {
+      env_range(P.offsets, e, P.n, b, t);
+      if (t > b) break;
+    }
+    j0 = b;
+  };
+  next_env();
+  bool load_g = true;
+  while (__any(e < e_end)) {
+    const bool active = e < e_end;
+    const int cnt = active ? static_cast<int>(t - j0 < GS ? t - j0 : GS) : 0;
+    __syncthreads();  // every read of the previous tiles of this wave is done
+    if (active && load_g) {
+      const T* ge = gc + e * NM * K;
+      for (int i = gl; i < NPC * K; i += GS) {
+        const int n = i / K;
+        const int k = i - n * K;
+        sG[k * NPC + n] = n < NM ? ge[i] : T(0);
+      }
+    }
+    if constexpr (STAGE) {
+      if (active) {
+        const T* src = R + j0 * (L + 1) * NM;
+        if (vec)
+          expand_tile_in<T, NPC, GS, true>(sR, RS, src, cnt, L, NM, gl);
+        else
+          expand_tile_in<T, NPC, GS, false>(sR, RS, src, cnt, L, NM, gl);
+      }
     }
     __syncthreads();
-    for (int64_t j = b + tid; j < t; j += kExpandThreads) {
-      const Point<T> pt = make_point<T, NORM>(xyz[j * 3], xyz[j * 3 + 1], xyz[j * 3 + 2]);
-      T prev[M + 3], cur[M + 3];
-#pragma unroll
-      for (int m = 0; m < M + 3; ++m) prev[m] = T(0);
-      T g0 = T(0), g1 = T(0), g2 = T(0);
-      const T* Rj = R + j * (L + 1) * NM;
-      auto row = [&](int l) {
-        q_row_any<T, M, CT>(l, pt.ez, pt.rxy2, cur);
-        T r[NPC], acc[NPC];
-#pragma unroll
-        for (int n = 0; n < NPC; ++n) {
-          r[n] = n < NM ? Rj[l * NM + n] : T(0);
-          acc[n] = T(0);
+    const int64_t j = j0 + gl;
+    if (active && gl < cnt) {
+      if constexpr (STAGE)
+        expand_bwd_point<T, MM, NORM, NPC, 0>(xyz, R, sG, sR + gl * RS, gxyz, gR, j, L, NM);
+      else if (vec)
+        expand_bwd_point<T, MM, NORM, NPC, 1>(xyz, R, sG, nullptr, gxyz, gR, j, L, NM);
+      else
+        expand_bwd_point<T, MM, NORM, NPC, 2>(xyz, R, sG, nullptr, gxyz, gR, j, L, NM);
+    }
+    if constexpr (STAGE) {
+      if (gR != nullptr) {
+        __syncthreads();  // the group's grad_R rows are in the tile
+        if (active) {
+          T* dst = gR + j0 * (L + 1) * NM;
+          if (vec)
+            expand_tile_out<T, NPC, GS, true>(sR, RS, dst, cnt, L, NM, gl);
+          else
+            expand_tile_out<T, NPC, GS, false>(sR, RS, dst, cnt, L, NM, gl);
         }
-        const int kb = l * l;
-        emit_row<T, M, 0, NORM>(l, prev, cur, pt.ex, pt.ey, pt.ez, pt.inv_r, [&](int k, T v) {
-          const V* gv = reinterpret_cast<const V*>(sG + k * NPC);
-          T gy = T(0);
-#pragma unroll
-          for (int h = 0; h < NPC / W; ++h) {
-            const V g = gv[h];
-#pragma unroll
-            for (int u = 0; u < W; ++u) {
-              gy += g[u] * r[h * W + u];
-              acc[h * W + u] += g[u] * v;
-            }
-          }
-          sT[k - kb] = gy;
-        });
-        if (gR != nullptr) {
-          T* out = gR + (j * (L + 1) + l) * NM;
-#pragma unroll
-          for (int n = 0; n < NPC; ++n)
-            if (n < NM) out[n] = acc[n];
-        }
-        emit_row<T, M, 1, NORM>(l, prev, cur, pt.ex, pt.ey, pt.ez, pt.inv_r,
-                                [&](int k, T d) { g0 += sT[k - kb] * d; });
-        emit_row<T, M, 2, NORM>(l, prev, cur, pt.ex, pt.ey, pt.ez, pt.inv_r,
-                                [&](int k, T d) { g1 += sT[k - kb] * d; });
-        emit_row<T, M, 3, NORM>(l, prev, cur, pt.ex, pt.ey, pt.ez, pt.inv_r,
-                                [&](int k, T d) { g2 += sT[k - kb] * d; });
-#pragma unroll
-        for (int m = 0; m < M + 3; ++m) prev[m] = cur[m];  // row l - 1 of the next degree
-      };
-      if constexpr (CT) {
-#pragma unroll
-        for (int l = 0; l <= LT; ++l) row(l);
-      } else {
-        for (int l = 0; l <= L; ++l) row(l);
       }
-      if (gxyz != nullptr) {
-        gxyz[j * 3 + 0] = g0;
-        gxyz[j * 3 + 1] = g1;
-        gxyz[j * 3 + 2] = g2;
+    }
+    // advance the group: next chunk, else the next environment
+    load_g = false;
+    if (active) {
+      j0 += GS;
+      if (j0 >= t) {
+        ++e;
+        next_env();
+        load_g = true;
       }
     }
   }

@@ -10,9 +10,6 @@ using T = float;
 
 // l_max <= 12: compile-time degrees; larger: the run-time-degree kernel of
 // the m-extent bucket.
-// The backward unrolls four rows per degree: compile-time degrees up to 8
-// (beyond that the fully unrolled kernel spills).
-constexpr int kBwdSpecMax = 8;
 constexpr int kSpecMax = 12;
 
 template <bool NORM, int ACC, int... Is>
@@ -27,32 +24,25 @@ void fill_spec(const void** out, std::integer_sequence<int, Ls...>) {
   for (size_t i = 0; i < sizeof...(Ls); ++i) out[i] = tbl[i];
 }
 
-template <bool NORM, int NPC, int... Is>
+template <bool NORM, int NPC, int GS, bool STAGE, int... Is>
 void fill_bwd(const void** out, std::integer_sequence<int, Is...>) {
-  const void* tbl[] = {reinterpret_cast<const void*>(&k_expand_bwd<T, kBuckets[Is], -1, NORM, NPC>)...};
+  const void* tbl[] = {reinterpret_cast<const void*>(&k_expand_bwd<T, kBuckets[Is], NORM, NPC, GS, STAGE>)...};
   for (size_t i = 0; i < sizeof...(Is); ++i) out[i] = tbl[i];
-}
-
-template <bool NORM, int NPC, int... Ls>
-void fill_bwd_spec(const void** out, std::integer_sequence<int, Ls...>) {
-  const void* tbl[] = {reinterpret_cast<const void*>(&k_expand_bwd<T, Ls, Ls, NORM, NPC>)...};
-  for (size_t i = 0; i < sizeof...(Ls); ++i) out[i] = tbl[i];
 }
 
 struct Tables {
   const void* fn[2][2][kNumBuckets];  // [normalize][ACC == 8]
   const void* spec[2][2][kSpecMax + 1];
-  const void* bwd[2][2][kNumBuckets];  // [normalize][NPC == 16]
-  const void* bwd_spec[2][2][kBwdSpecMax + 1];
+  const void* bwd[2][2][2][kNumBuckets];  // [normalize][NPC == 16][staged two groups, or one direct group]
   Tables() {
-    fill_bwd<false, 8>(bwd[0][0], std::make_integer_sequence<int, kNumBuckets>{});
-    fill_bwd<true, 8>(bwd[1][0], std::make_integer_sequence<int, kNumBuckets>{});
-    fill_bwd<false, 16>(bwd[0][1], std::make_integer_sequence<int, kNumBuckets>{});
-    fill_bwd<true, 16>(bwd[1][1], std::make_integer_sequence<int, kNumBuckets>{});
-    fill_bwd_spec<false, 8>(bwd_spec[0][0], std::make_integer_sequence<int, kBwdSpecMax + 1>{});
-    fill_bwd_spec<true, 8>(bwd_spec[1][0], std::make_integer_sequence<int, kBwdSpecMax + 1>{});
-    fill_bwd_spec<false, 16>(bwd_spec[0][1], std::make_integer_sequence<int, kBwdSpecMax + 1>{});
-    fill_bwd_spec<true, 16>(bwd_spec[1][1], std::make_integer_sequence<int, kBwdSpecMax + 1>{});
+    fill_bwd<false, 8, 32, true>(bwd[0][0][0], std::make_integer_sequence<int, kNumBuckets>{});
+    fill_bwd<true, 8, 32, true>(bwd[1][0][0], std::make_integer_sequence<int, kNumBuckets>{});
+    fill_bwd<false, 16, 32, true>(bwd[0][1][0], std::make_integer_sequence<int, kNumBuckets>{});
+    fill_bwd<true, 16, 32, true>(bwd[1][1][0], std::make_integer_sequence<int, kNumBuckets>{});
+    fill_bwd<false, 8, 64, false>(bwd[0][0][1], std::make_integer_sequence<int, kNumBuckets>{});
+    fill_bwd<true, 8, 64, false>(bwd[1][0][1], std::make_integer_sequence<int, kNumBuckets>{});
+    fill_bwd<false, 16, 64, false>(bwd[0][1][1], std::make_integer_sequence<int, kNumBuckets>{});
+    fill_bwd<true, 16, 64, false>(bwd[1][1][1], std::make_integer_sequence<int, kNumBuckets>{});
     fill_expand<false, 4>(fn[0][0], std::make_integer_sequence<int, kNumBuckets>{});
     fill_expand<true, 4>(fn[1][0], std::make_integer_sequence<int, kNumBuckets>{});
     fill_expand<false, 8>(fn[0][1], std::make_integer_sequence<int, kNumBuckets>{});
@@ -84,9 +74,13 @@ KernelInfo expand_bwd_info_f32(int L, int normalize, int n_max) {
     return KernelInfo{nullptr, 0, 0, 0, 0};
   const Tables& t = tables();
   const int w = n_max > 8 ? 1 : 0;
-  const void* fn = L <= kBwdSpecMax ? t.bwd_spec[normalize][w][L] : t.bwd[normalize][w][bucket_index(L)];
   const int npc = w ? 16 : 8;
-  return KernelInfo{fn, expand_bwd_lds_bytes<T>(L, npc), 0, npc, kExpandThreads};
+  // two staged groups of 32 lanes per wave where their G slices and radial
+  // tiles fit 64 KiB, else one group of 64 lanes reading its rows directly
+  const int direct = expand_bwd_lds_bytes<T>(L, npc, 32, true) > 64 * 1024 ? 1 : 0;
+  const int gs = direct ? 64 : 32;
+  return KernelInfo{t.bwd[normalize][w][direct][bucket_index(L)], expand_bwd_lds_bytes<T>(L, npc, gs, !direct), 0,
+                    64 / gs, kWave};
 }
 
 }  // namespace sph

@@ -44,6 +44,14 @@ struct DbwdParams {
   void* gxyz2; // nullable
 };
 
+// Explicit Hessians (k_hess).
+struct HessParams {
+  const void* xyz;  // [n,3]
+  int64_t n;
+  int32_t L;
+  void* d2Y;        // [n,3,3,K]
+};
+
 // Radial expansion over CSR environments (k_expand).
 struct ExpandParams {
   const void* xyz;         // [n,3]
@@ -97,12 +105,23 @@ struct ExpandBwdParams {
   void* gR;                // [n, L+1, n_max] or null
   int32_t* status;         // device status word or null
 };
-// LDS of one backward block: the environment's upstream gradient [K][np]
-// and one row of per-degree partial results per thread.
+// Row stride (elements) of the backward's LDS radial tile: (L+1) * np
+// channels, padded so that a row spans an odd number of 16-byte vectors
+// (lanes reading their rows as 16-byte vectors hit distinct banks).
 template <typename T>
-__host__ __device__ constexpr size_t expand_bwd_lds_bytes(int L, int np) {
+__host__ __device__ constexpr int expand_bwd_row_stride(int L, int np) {
+  constexpr int W = 16 / static_cast<int>(sizeof(T));
+  const int s = (L + 1) * np;
+  return (s / W) % 2 == 1 ? s : s + W;
+}
+// LDS of one backward block (one wave in groups of gs lanes): each group's
+// environment gradient G as [K][np] and, when staged, its radial tile of gs
+// rows.
+template <typename T>
+__host__ __device__ constexpr size_t expand_bwd_lds_bytes(int L, int np, int gs, bool stage) {
   const int K = (L + 1) * (L + 1);
-  return sizeof(T) * (static_cast<size_t>(K) * np + 128 * static_cast<size_t>((2 * L + 1) | 1));
+  const size_t per = static_cast<size_t>(K) * np + (stage ? static_cast<size_t>(gs) * expand_bwd_row_stride<T>(L, np) : 0);
+  return sizeof(T) * static_cast<size_t>(64 / gs) * per;
 }
 
 // A kernel's host stub, its dynamic LDS bytes (for the l_max it was looked
@@ -158,6 +177,11 @@ KernelInfo bwd_info_f32(int L);
 KernelInfo bwd_info_f64(int L);
 KernelInfo dbwd_info_f32(int L, int normalize);
 KernelInfo dbwd_info_f64(int L, int normalize);
+// Explicit Hessians: the run-time-degree kernel of the m-extent bucket of L,
+// with a two-wave degree-split block where the nine rows of a point fit one
+// group of degrees; tile_points = 16.
+KernelInfo hess_info_f32(int L, int normalize);
+KernelInfo hess_info_f64(int L, int normalize);
 // Radial expansion: the compile-time kernel of L (float L <= 12, double
 // L <= 8), else the one of the m-extent bucket of L (run-time degree), with
 // the accumulator width expand_acc(L, n_max);

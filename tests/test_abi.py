@@ -29,7 +29,8 @@ def lib():
 def test_header_declares_the_documented_entry_points():
     names = header_functions()
     for required in ("sph_compute", "sph_compute_with_gradients", "sph_backward",
-                     "sph_double_backward", "sph_batched_compute", "sph_radial_expansion"):
+                     "sph_double_backward", "sph_batched_compute", "sph_radial_expansion",
+                     "sph_compute_with_hessians"):
         assert required in names
 
 
@@ -72,6 +73,30 @@ def test_compute_validation(lib, args, code):
     assert lib.sph_compute(*args) == code
     if code:
         assert len(lib.sph_last_error()) > 0
+
+
+@pytest.mark.parametrize("args,code", [
+    ((FAKE, -1, 4, 0, 0, FAKE, None, FAKE, None), 2),      # n < 0
+    ((FAKE, 10, 33, 0, 0, FAKE, None, FAKE, None), 3),     # l_max too large
+    ((FAKE, 10, 4, 3, 0, FAKE, None, FAKE, None), 2),      # normalize not 0/1
+    ((FAKE, 10, 4, 0, 2, FAKE, None, FAKE, None), 2),      # bad dtype
+    ((None, 10, 4, 0, 0, FAKE, None, FAKE, None), 1),      # xyz NULL
+    ((FAKE, 10, 4, 0, 0, None, None, FAKE, None), 1),      # Y NULL
+    ((FAKE, 10, 4, 0, 0, FAKE, None, None, None), 1),      # d2Y NULL
+    ((None, 0, 4, 0, 0, None, None, None, None), 0),       # n = 0: nothing to do
+])
+def test_hessian_validation(lib, args, code):
+    assert lib.sph_compute_with_hessians(*args) == code
+    if code:
+        assert len(lib.sph_last_error()) > 0
+
+
+def test_hessian_overlap_is_rejected(lib):
+    base = 0x200000
+    # d2Y [10,3,3,25] float starting inside Y [10,25]
+    st = lib.sph_compute_with_hessians(ctypes.c_void_p(0x100000), 10, 4, 1, 0, ctypes.c_void_p(base), None,
+                                       ctypes.c_void_p(base + 400), None)
+    assert st == 2 and b"overlaps" in lib.sph_last_error()
 
 
 def test_overlap_is_rejected(lib):
@@ -152,5 +177,3 @@ def test_radial_expansion_backward_validation(lib):
     assert x(FAKE, FAKE, 3, 10, FAKE, 8, 4, 1, 0, None, FAKE, None, None, None) == 1    # grad_c NULL
     assert x(FAKE, FAKE, 3, 10, FAKE, 8, 40, 1, 0, FAKE, FAKE, None, None, None) == 3   # l_max
     assert x(FAKE, FAKE, 3, 10, FAKE, 8, 4, 1, 0, FAKE, None, None, None, None) == 0    # nothing requested
-    assert x(FAKE, FAKE, 3, 10, FAKE, 16, 30, 1, 1, FAKE, FAKE, None, None, None) == 2  # LDS
-    assert b"LDS" in lib.sph_last_error()

@@ -194,11 +194,15 @@ def _check_backward(gx, gR, pts, offs, R, G, l_max, normalize, dt, label=""):
 @pytest.mark.parametrize("dt", [torch.float32, torch.float64])
 @pytest.mark.parametrize("l_max,n_max,normalize", [
     (0, 1, True), (2, 3, False), (4, 8, True), (8, 8, True), (8, 5, False), (8, 16, True), (11, 4, True),
-    (20, 9, True)])
+    (20, 9, True),
+    # one 64-lane group per wave (two groups' LDS would pass 64 KiB)
+    (28, 12, True)])
 def test_expansion_backward_matches_oracle(dt, l_max, n_max, normalize):
     import paper_2302_08381_amd as sph
     print(f"expansion backward {dt} l_max={l_max} n_max={n_max} normalize={normalize}", flush=True)
-    counts = [0, 1, 7, 64, 129, 0, 200] if l_max <= 12 else [0, 1, 9, 40]
+    # environments across the 32- and 64-point chunk edges of the lane groups,
+    # and one far longer than the rest (the groups split the points evenly)
+    counts = [0, 1, 7, 32, 33, 64, 129, 0, 200, 1500, 3] if l_max <= 12 else [0, 1, 9, 40, 70]
     pts, offs, R = _case(counts, l_max, n_max, 500 + 7 * l_max + n_max)
     xyz = to_dev(pts, dt)
     Rt = to_dev(R, dt)

@@ -279,12 +279,12 @@ def test_precision_stress_mix_finite():
 
 
 # ---------------------------------------------------------------- Hessians
+@pytest.mark.parametrize("L", [8, 12])
 @pytest.mark.parametrize("normalize", [False, True])
-def test_hessian_invariants(normalize):
+def test_hessian_invariants(normalize, L):
     """Symmetric; trace 0 for the solid harmonics (they are harmonic) and
     -l(l+1) Y / r^2 for the normalised ones; Euler: H x = (l-1) grad for solid."""
     pts = np.concatenate([_pts(12, 26), _near_pole(4, 27)])
-    L = 8
     Y, G, H = oracle.definition_eval_ld(pts, L, normalize, hessian=True)
     np.testing.assert_array_equal(np.asarray(H, float), np.asarray(np.swapaxes(H, 1, 2), float))
     tr = H[:, 0, 0] + H[:, 1, 1] + H[:, 2, 2]
@@ -300,10 +300,13 @@ def test_hessian_invariants(normalize):
         assert (err / g[:, None, :]).max() < 1e-14
 
 
+@pytest.mark.parametrize("L", [6, 12])
 @pytest.mark.parametrize("normalize", [False, True])
-def test_hessian_vs_differences_of_gradient(normalize):
+def test_hessian_vs_differences_of_gradient(normalize, L):
+    """The definition tier's exact Hessians against central differences of
+    the bulk tier's gradients (an independent route), up to l = 12, the
+    range the GPU Hessian tests compare against."""
     pts = np.concatenate([_pts(8, 28), _near_pole(4, 29)]).astype(LD)
-    L = 6
     _, _, H = oracle.definition_eval_ld(pts, L, normalize, hessian=True)
     _, _, hs = oracle.component_scales(np.asarray(pts, float), L, normalize)
     h = LD("1e-6")
