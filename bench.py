@@ -38,8 +38,10 @@ L_MAX = 8
 NORMALIZE = True
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 METRIC = "points/s and HBM GB/s for Y+dY fwd+bwd, l_max=8 FP32; max err vs FP64 oracle"
-KERNEL_SOURCES = ["sph_device.hpp", "sph_coeffs.hpp", "sph_fwd.inl", "sph_fwd4.inl", "sph_bwd.inl", "sph_launch.hpp",
-                  "sph_instances.inl", "sph_api.cpp"]
+# The sources of the headline step's two kernels (their code, tables and
+# launch shapes): a change to any of them voids the committed byte counters.
+KERNEL_SOURCES = ["sph_device.hpp", "sph_coeffs.hpp", "sph_fwd.inl", "sph_fwd4.inl", "sph_bwd.inl",
+                  "sph_instances.inl", "sph_kernels_derivs_f32_n1_m0.hip", "sph_kernels_bwd_f32.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_l8_f32.json")
 
 
@@ -365,7 +367,14 @@ def extras(dev):
     tb3 = _time(lambda: sph.sph_backward(dY3, gYb, L3, grad_xyz=gx3), 10)
     out["backward_l6_f32_4M"] = {"s": tb3, "points_per_s": n3 / tb3,
                                  "GB_per_s": n3 * 4 * (4 * K3 + 3) / tb3 / 1e9}
-    del xb, gYb, vb, Y3, dY3, gx3
+    # explicit second derivatives on the same points: Y, dY and d2Y [n,3,3,K]
+    # (two launches: the forward, then the second-derivative kernel)
+    d2Y3 = torch.empty((n3, 3, 3, K3), device=dev)
+    th = _time(lambda: sph.sph_compute_with_hessians(xb, L3, True, Y=Y3, dY=dY3, d2Y=d2Y3), 5)
+    out["hessians_l6_f32_4M"] = {"s": th, "points_per_s": n3 / th,
+                                 "GB_per_s": n3 * 4 * (3 + 13 * K3) / th / 1e9,
+                                 "bytes": "read xyz, write Y, dY and d2Y: N*4*(3 + 13K)"}
+    del xb, gYb, vb, Y3, dY3, gx3, d2Y3
     # plain method, CPU-sized: N = 1000, float64, l_max = 4 (launch-bound)
     x1 = torch.as_tensor(standard_normal_points(1000, SEEDS["plain_cpu"]), dtype=torch.float64).to(dev)
     t1 = _time(lambda: sph.sph_compute_with_gradients(x1, 4, True), 50)
@@ -454,6 +463,216 @@ def extras(dev):
         spec[str(Ls)] = row
     out["compile_time_vs_runtime_degree_f32"] = spec
     return out
+
+
+# ------------------------------------------------------------ kernel suite profile
+# One program that launches every kernel of the path on its workload, for
+# rocprofv3 runs: a kernel trace, the two HBM byte counters, and the SQ
+# counters that show what bounds each kernel (VALU activity, occupancy, LDS
+# bank conflicts).  Counters are collected in runs of their own.
+SUITE_COMMANDS = {
+    "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d {out}/suite_trace -o run -- "
+             "python3 {repo}/bench.py --profile-suite --steps 5 --warmup 2",
+    "fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d {out}/suite_fetch -o run -- "
+             "python3 {repo}/bench.py --profile-suite --steps 2 --warmup 1",
+    "write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d {out}/suite_write -o run -- "
+             "python3 {repo}/bench.py --profile-suite --steps 2 --warmup 1",
+    "sq": "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_WAVE_CYCLES SQ_LDS_BANK_CONFLICT "
+          "SQ_INSTS_LDS SQ_BUSY_CYCLES GRBM_GUI_ACTIVE --output-format csv -d {out}/suite_sq -o run -- "
+          "python3 {repo}/bench.py --profile-suite --steps 2 --warmup 1",
+    "tcc": "rocprofv3 --pmc TCC_EA0_WRREQ_sum TCC_EA0_WRREQ_64B_sum TCC_EA0_WRREQ_LEVEL_sum GRBM_GUI_ACTIVE "
+           "--output-format csv -d {out}/suite_tcc -o run -- "
+           "python3 {repo}/bench.py --profile-suite --steps 2 --warmup 1",
+}
+SUITE_STEPS = 5  # the --steps of the trace command
+
+
+def _suite_workloads():
+    """(role, kernel-name tag, algorithmic bytes per launch, workload) of the
+    suite's kernels."""
+    from workloads import SEEDS, csr_environments
+    K8, K6 = 81, 49
+    n3 = 4_000_000
+    _, offs = csr_environments(20_000, 8, 128, 0.5, 5.0, SEEDS["batched"])
+    ne, npt = offs.size - 1, int(offs[-1])
+    L, NM = EXPANSION_L, EXPANSION_CHANNELS
+    return [
+        ("forward", "k_fwd4<float, 8, 8,", N_POINTS * 4 * (3 + 4 * K8),
+         "Y+dY, N = 1e6, l_max = 8, float32, normalised"),
+        ("backward", "k_bwd<float", N_POINTS * 4 * (4 * K8 + 3), "grad_xyz from dY, same workload"),
+        ("double backward", "k_dbwd<float", n3 * 4 * ((3 + K6 + 3) + (K6 + 3)),
+         "ggY and grad_xyz2, N = 4e6 in the ball 0.5..5, l_max = 6, float32, normalised"),
+        ("hessian: Y+dY", "k_fwd4<float, 6, 6,", n3 * 4 * (3 + 4 * K6),
+         "the forward half of sph_compute_with_hessians, same 4e6 points, l_max = 6"),
+        ("hessian: d2Y", "k_hess<float", n3 * 4 * (3 + 9 * K6), "d2Y [n,3,3,K], same points"),
+        ("radial expansion", "k_expand<float", npt * 4 * (3 + (L + 1) * NM) + ne * (8 + 4 * NM * K8),
+         f"{ne} environments ({npt} points), l_max = 8, 8 channels, float32"),
+        ("radial expansion backward", "k_expand_bwd<float",
+         npt * 4 * (3 + 2 * (L + 1) * NM + 3) + ne * (8 + 4 * NM * K8), "grad_xyz and grad_R, same environments"),
+    ]
+
+
+def suite_hash() -> str:
+    """Hash of every kernel source and the C ABI (the suite covers all of them)."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2302_08381_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+CU_NUM, XCD_NUM, CLOCK_GHZ = 256, 8, 2.4
+
+
+def _per_dispatch(path: str) -> dict:
+    """{dispatch id: (kernel name, {counter: value}, row)} from a rocprofv3
+    counter CSV (one row per dispatch and counter)."""
+    import csv
+    out = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            d = out.setdefault(int(r["Dispatch_Id"]), (r["Kernel_Name"], {}, r))
+            d[1][r["Counter_Name"]] = d[1].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    return out
+
+
+def summarize_suite(outdir: str) -> None:
+    """profiles/kernel_suite.md: per kernel of the path, its mean duration
+    (kernel trace), algorithmic and HBM bytes (FETCH_SIZE / WRITE_SIZE scaled
+    by the 1 GiB reference copy), and what the SQ counters say bounds it:
+    VALU instructions per wave and the share of the CUs' VALU issue slots
+    they fill, mean resident waves per CU, LDS instructions and bank-conflict
+    cycles.  GRBM_GUI_ACTIVE is summed over the 8 XCDs, so the kernel's
+    cycles are GRBM_GUI_ACTIVE / 8; SQ_WAVE_CYCLES counts quad-cycles."""
+    import csv
+    cmds = {k: v.format(out="/root/repo/gpurun_out", repo="/root/repo") for k, v in SUITE_COMMANDS.items()}
+    with open(os.path.join(outdir, "suite_trace", "run_kernel_trace.csv")) as f:
+        trace = list(csv.DictReader(f))
+    fetch = _per_dispatch(os.path.join(outdir, "suite_fetch", "run_counter_collection.csv"))
+    write = _per_dispatch(os.path.join(outdir, "suite_write", "run_counter_collection.csv"))
+    sq = _per_dispatch(os.path.join(outdir, "suite_sq", "run_counter_collection.csv"))
+    tcc_path = os.path.join(outdir, "suite_tcc", "run_counter_collection.csv")
+    tcc = _per_dispatch(tcc_path) if os.path.exists(tcc_path) else {}
+
+    def mean_counter(tbl, tag, name):
+        v = [c[name] for k, c, _ in tbl.values() if tag in k and name in c]
+        return sum(v) / len(v) if v else None
+
+    fs = REFERENCE_COPY_BYTES / (mean_counter(fetch, REFERENCE_COPY, "FETCH_SIZE") * 1024)
+    ws = REFERENCE_COPY_BYTES / (mean_counter(write, REFERENCE_COPY, "WRITE_SIZE") * 1024)
+    lines = ["# Kernel suite: time, bytes and SQ counters of every kernel of the path", "",
+             "Commands (from /tmp, TMPDIR=/tmp), each in a run of its own:", ""]
+    lines += ["    " + cmds[k] for k in ("trace", "fetch", "write", "sq") + (("tcc",) if tcc else ())]
+    # the hash the profiled runs printed (the sources they ran), not the tree's
+    run_hashes = set()
+    for k in ("trace", "fetch", "write", "sq", "tcc"):
+        log = os.path.join(outdir, f"suite_{k}.log")
+        if os.path.exists(log):
+            with open(log) as f:
+                for line in f:
+                    if line.startswith('{"profile_run": "suite"'):
+                        run_hashes.add(json.loads(line)["kernel_sources"])
+    if len(run_hashes) != 1:
+        raise SystemExit(f"suite runs printed kernel source hashes {sorted(run_hashes)}: expected exactly one")
+    run_hash = run_hashes.pop()
+    note = "" if run_hash == suite_hash() else " (the sources have changed since: the figures are of the earlier ones)"
+    lines += ["", f"Kernel sources hash: {run_hash}{note}", "",
+              f"HBM bytes = counter KiB * 1024 * factor, the factor set so that the 1 GiB reference copy reads and "
+              f"writes 1 GiB: FETCH_SIZE x{fs:.3f}, WRITE_SIZE x{ws:.3f}.  Cycles = GRBM_GUI_ACTIVE / {XCD_NUM} "
+              f"(the counter is summed over the XCDs).  VALU slots: one wave64 VALU instruction per SIMD per 4 "
+              f"cycles, i.e. one per CU per cycle over {CU_NUM} CUs.  Waves per CU: 4 * SQ_WAVE_CYCLES "
+              f"(quad-cycles) / ({CU_NUM} * cycles), of at most 32.  LDS conflict: SQ_LDS_BANK_CONFLICT cycles "
+              f"per CU-cycle.", "",
+              "| kernel | workload | mean us | alg. bytes | alg. GB/s | HBM bytes / alg. | VALU instr / wave | "
+              "VALU slots used | waves / CU | LDS instr / wave | LDS conflict | VGPR, AGPR | block x grid |",
+              "|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    for role, tag, alg, what in _suite_workloads():
+        ds = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r) for r in trace if tag in r["Kernel_Name"])
+        ds = ds[-SUITE_STEPS:]
+        if not ds:
+            continue
+        mean = sum(e - b for b, e, _ in ds) / len(ds) * 1e-9
+        row = ds[-1][2]
+        fk, wk = mean_counter(fetch, tag, "FETCH_SIZE"), mean_counter(write, tag, "WRITE_SIZE")
+        hbm = (fk * fs + wk * ws) * 1024 if fk is not None and wk is not None else None
+        c = {n: mean_counter(sq, tag, n) for n in ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_WAVE_CYCLES", "SQ_INSTS_LDS",
+                                                  "SQ_LDS_BANK_CONFLICT", "GRBM_GUI_ACTIVE")}
+        cyc = c["GRBM_GUI_ACTIVE"] / XCD_NUM
+        lines.append(
+            f"| {role} (`{row['Kernel_Name'].split('(')[0].replace('void sph::', '')}`) | {what} | {mean * 1e6:.1f} | "
+            f"{alg:.4g} | {alg / mean / 1e9:.0f} | {hbm / alg:.3f} | {c['SQ_INSTS_VALU'] / c['SQ_WAVES']:.0f} | "
+            f"{100 * c['SQ_INSTS_VALU'] / (CU_NUM * cyc):.0f} % | {4 * c['SQ_WAVE_CYCLES'] / (CU_NUM * cyc):.1f} | "
+            f"{c['SQ_INSTS_LDS'] / c['SQ_WAVES']:.0f} | {100 * c['SQ_LDS_BANK_CONFLICT'] / (CU_NUM * cyc):.1f} % | "
+            f"{row['VGPR_Count']}, {row['Accum_VGPR_Count']} | {row['Workgroup_Size_X']} x "
+            f"{int(row['Grid_Size_X']) // max(1, int(row['Workgroup_Size_X']))} |")
+    lines += ["", "Means over the last %d launches of each kernel in the trace run; counters from the last "
+              "launches of the counter runs (counter runs serialise the launches)." % SUITE_STEPS]
+    if tcc:
+        # write path to HBM: requests from L2 to the memory fabric and how many
+        # are in flight on average, for the store-bound kernels and torch's
+        # fill of 1 GiB (the write-only reference of the same run)
+        lines += ["", "Writes from L2 to memory (TCC_EA0_WRREQ: requests, of them 64-byte; WRREQ_LEVEL: "
+                  "requests in flight summed over cycles, so LEVEL / cycles is the mean number in flight):", "",
+                  "| kernel | mean us | write requests | 64-byte share | mean in flight | written GB/s |",
+                  "|---|---|---|---|---|---|"]
+        refs = [(r, t, a) for r, t, a, _ in _suite_workloads() if r in ("forward", "hessian: d2Y",
+                                                                        "hessian: Y+dY")]
+        refs.append(("torch fill, 1 GiB", "FillFunctor", float(REFERENCE_COPY_BYTES)))
+        for role, tag, alg in refs:
+            ds = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in trace if tag in r["Kernel_Name"])
+            ds = ds[-SUITE_STEPS:]
+            req = mean_counter(tcc, tag, "TCC_EA0_WRREQ_sum")
+            if not ds or req is None:
+                continue
+            mean = sum(e - b for b, e in ds) / len(ds) * 1e-9
+            r64 = mean_counter(tcc, tag, "TCC_EA0_WRREQ_64B_sum")
+            lvl = mean_counter(tcc, tag, "TCC_EA0_WRREQ_LEVEL_sum")
+            cyc = mean_counter(tcc, tag, "GRBM_GUI_ACTIVE") / XCD_NUM
+            wk = mean_counter(write, tag, "WRITE_SIZE")
+            wgbs = f"{wk * ws * 1024 / mean / 1e9:.0f}" if wk is not None else ""
+            lines.append(f"| {role} | {mean * 1e6:.1f} | {req:.4g} | {r64 / req:.3f} | {lvl / cyc:.0f} | {wgbs} |")
+    with open(os.path.join(ROOT, "profiles", "kernel_suite.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def profile_suite(dev, steps: int, warmup: int) -> None:
+    import torch
+
+    import paper_2302_08381_amd as sph
+    from workloads import SEEDS, shell_points, standard_normal, standard_normal_points
+    K = 81
+    x = torch.as_tensor(standard_normal_points(N_POINTS, SEEDS["plain_gpu"]), dtype=torch.float32).to(dev)
+    gY = torch.as_tensor(standard_normal((N_POINTS, K), SEEDS["plain_gpu_grad"]), dtype=torch.float32).to(dev)
+    Y = torch.empty((N_POINTS, K), device=dev)
+    dY = torch.empty((N_POINTS, 3, K), device=dev)
+    gx = torch.empty((N_POINTS, 3), device=dev)
+    n3, L3, K3 = 4_000_000, 6, 49
+    xb = torch.as_tensor(shell_points(n3, 0.5, 5.0, SEEDS["diff"]), dtype=torch.float32).to(dev)
+    gYb = torch.as_tensor(standard_normal((n3, K3), 31), dtype=torch.float32).to(dev)
+    vb = torch.as_tensor(standard_normal((n3, 3), 32), dtype=torch.float32).to(dev)
+    Y3 = torch.empty((n3, K3), device=dev)
+    dY3 = torch.empty((n3, 3, K3), device=dev)
+    d2Y3 = torch.empty((n3, 3, 3, K3), device=dev)
+    xe, oe, Re, Ge, ne_pts, ne = _expansion_inputs(dev)
+    ce = torch.empty((ne, EXPANSION_CHANNELS, K), device=dev)
+
+    def step():
+        sph.sph_compute_with_gradients(x, L_MAX, True, Y=Y, dY=dY)
+        sph.sph_backward(dY, gY, L_MAX, grad_xyz=gx)
+        sph.sph_double_backward(xb, gYb, vb, L3, True)
+        sph.sph_compute_with_hessians(xb, L3, True, Y=Y3, dY=dY3, d2Y=d2Y3)
+        sph.sph_radial_expansion(xe, oe, Re, EXPANSION_L, True, out=ce, check=False)
+        sph.sph_radial_expansion_backward(xe, oe, Re, Ge, EXPANSION_L, True, check=False)
+    for _ in range(warmup + steps):
+        step()
+    # reference copy of known size for scaling the HBM byte counters
+    a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_run": "suite", "steps": steps, "kernel_sources": suite_hash()}), flush=True)
 
 
 # ------------------------------------------------------------ precision report
@@ -550,8 +769,6 @@ def precision_report(dev, pool, path: str, per_class: int = 20_000, chunk: int =
     print("\n".join(table_head + summary), flush=True)
 
 
-EXPANSION_PROFILE_COMMAND = ("rocprofv3 --kernel-trace --stats --output-format csv -d {out}/prof_expand -o run -- "
-                             "python3 {repo}/bench.py --profile-expansion --steps 20 --warmup 3")
 EXPANSION_L, EXPANSION_CHANNELS = 8, 8
 
 
@@ -570,56 +787,6 @@ def _expansion_inputs(dev):
     return xyz, o, R, G, int(offs[-1]), int(np.asarray(offs).size - 1)
 
 
-def profile_expansion(dev, steps: int, warmup: int) -> None:
-    import torch
-
-    import paper_2302_08381_amd as sph
-    xyz, o, R, G, n, n_env = _expansion_inputs(dev)
-    c = torch.empty((n_env, EXPANSION_CHANNELS, (EXPANSION_L + 1) ** 2), device=dev)
-
-    def step():
-        sph.sph_radial_expansion(xyz, o, R, EXPANSION_L, True, out=c, check=False)
-        sph.sph_radial_expansion_backward(xyz, o, R, G, EXPANSION_L, True, check=False)
-    for _ in range(warmup + steps):
-        step()
-    torch.cuda.synchronize()
-    print(json.dumps({"profile_run": "radial_expansion", "steps": steps, "points": n, "environments": n_env}))
-
-
-def summarize_expansion(outdir: str) -> None:
-    """profiles/expansion_l8_f32.md: kernel-trace means of the radial
-    expansion and its backward over the timed launches, with their
-    algorithmic bytes."""
-    import csv
-    from workloads import SEEDS, csr_environments
-    _, offs = csr_environments(20_000, 8, 128, 0.5, 5.0, SEEDS["batched"])
-    n, n_env = int(offs[-1]), offs.size - 1
-    L, NM = EXPANSION_L, EXPANSION_CHANNELS
-    K = (L + 1) ** 2
-    fwd_bytes = n * 4 * (3 + (L + 1) * NM) + n_env * (8 + 4 * NM * K)
-    bwd_bytes = n * 4 * (3 + 2 * (L + 1) * NM + 3) + n_env * (8 + 4 * NM * K)
-    with open(os.path.join(outdir, "prof_expand", "run_kernel_trace.csv")) as f:
-        trace = list(csv.DictReader(f))
-    cmd = EXPANSION_PROFILE_COMMAND.format(out="/root/repo/gpurun_out", repo="/root/repo")
-    lines = [f"# Kernel trace: radial expansion and its backward, l_max = {L}, {NM} channels, float32, "
-             f"{n_env} environments ({n} points)", "",
-             "Command (from /tmp, TMPDIR=/tmp):", "", "    " + cmd, "",
-             "Means over the last 20 launches of each kernel (the timed steps):", "",
-             "| kernel | launches | mean us | algorithmic bytes | algorithmic GB/s | points/s |",
-             "|---|---|---|---|---|---|"]
-    for tag, byts in (("k_expand<", fwd_bytes), ("k_expand_bwd<", bwd_bytes)):
-        rows = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"])
-                      for r in trace if tag in r["Kernel_Name"])[-20:]
-        if not rows:
-            continue
-        m = sum(e - b for b, e, _ in rows) / len(rows) * 1e-9
-        lines.append(f"| `{rows[0][2]}` | {len(rows)} | {m * 1e6:.1f} | {byts} | {byts / m / 1e9:.0f} | {n / m:.3g} |")
-    lines += ["", "Algorithmic bytes: forward N*4*(3 + (L+1)*n_max) + n_env*(8 + 4*n_max*K); backward "
-              "N*4*(3 + 2*(L+1)*n_max + 3) + n_env*(8 + 4*n_max*K)."]
-    with open(os.path.join(ROOT, "profiles", "expansion_l8_f32.md"), "w") as f:
-        f.write("\n".join(lines) + "\n")
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -631,20 +798,20 @@ def main():
                     help="only run warmup + steps (and a 1 GiB reference copy), for rocprofv3")
     ap.add_argument("--summarize", metavar="DIR",
                     help="write the profiles/ summaries from the rocprofv3 output in DIR (no GPU)")
-    ap.add_argument("--profile-expansion", action="store_true",
-                    help="only run the radial expansion and its backward (l_max = 8, the 20 000 batched "
-                         "environments, 8 channels, float32): warmup + steps, for rocprofv3")
+    ap.add_argument("--profile-suite", action="store_true",
+                    help="only run warmup + steps of every kernel of the path on its workload (and a 1 GiB "
+                         "reference copy), for rocprofv3")
+    ap.add_argument("--summarize-suite", metavar="DIR",
+                    help="write profiles/kernel_suite.md from the rocprofv3 output folders in DIR (no GPU)")
     ap.add_argument("--precision-report", metavar="PATH",
                     help="write the per-l accuracy tables of the l_max = 32 stress workload (float32 and float64, "
                          "per sub-population) to PATH")
-    ap.add_argument("--summarize-expansion", metavar="DIR",
-                    help="write profiles/expansion_l8_f32.md from the kernel trace in DIR/prof_expand (no GPU)")
     args = ap.parse_args()
     if args.summarize:
         summarize(args.summarize)
         return
-    if args.summarize_expansion:
-        summarize_expansion(args.summarize_expansion)
+    if args.summarize_suite:
+        summarize_suite(args.summarize_suite)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the path has no "
@@ -655,7 +822,7 @@ def main():
     # The oracle's worker processes are forked before anything touches the
     # GPU, so they hold no device state.
     pool = None
-    if args.precision_report or not (args.no_cpu_baseline or args.profile or args.profile_expansion):
+    if args.precision_report or not (args.no_cpu_baseline or args.profile or args.profile_suite):
         import multiprocessing as mp
         pool = mp.get_context("fork").Pool(host_cores())
 
@@ -666,8 +833,8 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    if args.profile_expansion:
-        profile_expansion(dev, args.steps, args.warmup)
+    if args.profile_suite:
+        profile_suite(dev, args.steps, args.warmup)
         return
     if args.precision_report:
         precision_report(dev, pool, args.precision_report)
@@ -697,7 +864,8 @@ def main():
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"profile_run": True, "steps": args.steps, "reference_copy_bytes_each_way": a.numel() * 4}))
+        print(json.dumps({"profile_run": True, "steps": args.steps, "reference_copy_bytes_each_way": a.numel() * 4,
+                          "kernel_sources": kernel_hash()}))
         return
 
     stream = torch.cuda.current_stream(dev)  # the launch stream of both kernels

@@ -32,6 +32,34 @@ __device__ __forceinline__ void env_range(const int64_t* o, int64_t e, int64_t n
   t = hi;
 }
 
+// First e in [0, n_env] with o[e] >= p, found by the W lanes base .. base+W-1
+// of the wave together: each round probes W evenly spaced offsets at once and
+// keeps the gap where the comparison turns, so log_W(n_env) rounds of one
+// dependent load replace log_2(n_env).  Every lane of the wave must call it
+// (it votes across the wave); each group gets its own answer.  With offsets
+// that are not sorted the result is still in [0, n_env].
+__device__ __forceinline__ int64_t group_lower_bound(const int64_t* o, int64_t n_env, int64_t p, int gl, int base,
+                                                     int W) {
+  int rounds = 1;  // the same for every lane: W^rounds > n_env
+  for (int64_t span = W; span <= n_env; span *= W) ++rounds;
+  const unsigned long long gmask = W == 64 ? ~0ull : ((1ull << W) - 1) << base;
+  int64_t lo = 0, hi = n_env;
+  for (int r = 0; r < rounds; ++r) {
+    const int64_t step = (hi - lo + W - 1) / W;
+    const int64_t q = lo + gl * step;
+    const bool less = step > 0 && q < hi && o[q] < p;
+    const int c = __popcll(__ballot(less) & gmask);
+    if (step > 0) {  // the answer is in (q_{c-1}, q_c]
+      const int64_t qc = lo + c * step;
+      const int64_t nhi = qc < hi ? qc : hi;
+      const int64_t nlo = c > 0 ? lo + (c - 1) * step + 1 : lo;
+      lo = nlo < nhi ? nlo : nhi;
+      hi = nhi;
+    }
+  }
+  return lo;
+}
+
 // Values of degrees [la, lb) of one point into its LDS row.  LT >= 0: the
 // degree loop is unrolled to LT with compile-time degrees (each row's
 // coefficients fold to literals), every row behind a uniform range check;
@@ -80,24 +108,40 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandParams P) {
     if (tid == 0) P.status[0] = all_ok ? 0 : 4 /* SPH_ERR_OFFSETS */;
   }
 
-  // The block walks its chunks (environment e = blockIdx.x, + gridDim.x,
-  // ...; points j0 .. j0 + JC of each) as a pipeline: the coordinates and
-  // the first radial batch of chunk i + 1 are loaded into registers while
-  // chunk i's harmonics are computed and contracted.  Indices past a chunk
-  // load its last element again (in bounds, never stored), which keeps the
-  // loads unconditional.  Empty environments get their zeros as the walk
-  // passes them.
+  // The blocks split the points evenly: block g of G takes the environments
+  // that start in points [g n / G, (g+1) n / G) (found by searching the
+  // offsets; every environment has one start, so each goes to exactly one
+  // block; see kEven for small l_max).  The block walks its chunks (points j0 .. j0 + JC of each
+  // environment) as a pipeline: the coordinates and the first radial batch
+  // of chunk i + 1 are loaded into registers while chunk i's harmonics are
+  // computed and contracted.  Indices past a chunk load its last element
+  // again (in bounds, never stored), which keeps the loads unconditional.
+  // Empty environments get their zeros as the walk passes them.
   constexpr int RB = kExpandRBatch<T>;
-  int64_t e = blockIdx.x, b = 0, t = 0, j0 = 0;
+  // Small l_max (the kernels whose items are split across threads) keeps
+  // the interleaved walk, environments blockIdx.x + i gridDim.x: there the
+  // even split measured 12 % slower (l_max 3: 98-103 against 85-91 us),
+  // while it is 8-11 % faster at l_max 8 and 12.
+  constexpr bool kEven = !(LT >= 0 && LT <= 4);
+  const int64_t G = gridDim.x, g = blockIdx.x;
+  int64_t e = g, e_end = P.n_env, b = 0, t = 0, j0 = 0;
+  const int64_t estep = kEven ? 1 : G;
+  if constexpr (kEven) {
+    // each wave finds both ends at once: lanes 0..31 the start, 32..63 the end
+    const int wl = tid % kWave, half = wl / 32;
+    const int64_t bound = group_lower_bound(P.offsets, P.n_env, (g + half) * P.n / G, wl % 32, half * 32, 32);
+    e = __shfl(bound, 0);
+    e_end = g + 1 == G ? P.n_env : __shfl(bound, 32);
+  }
   // moves (e, b, t, j0) to the next chunk at or after environment e (j0 =
   // start of e when fresh); false when the block has no chunk left
   auto seek = [&](bool fresh) {
     if (!fresh) {
       j0 += JC;
       if (j0 < t) return true;
-      e += gridDim.x;
+      e += estep;
     }
-    for (; e < P.n_env; e += gridDim.x) {
+    for (; e < e_end; e += estep) {
       env_range(P.offsets, e, P.n, b, t);
       j0 = b;
       if (t > b) return true;
@@ -611,23 +655,14 @@ __global__ __launch_bounds__(kWave) void k_expand_bwd(ExpandBwdParams P) {
   }
 
   // The groups split the points evenly: group g of G takes the environments
-  // that start in points [g n / G, (g+1) n / G) (found by binary search in
-  // the offsets; every environment has one start, so each goes to exactly
-  // one group), which keeps the two groups of a wave and all waves equally
-  // busy.  Group state: environment e (up to e_end), its range [b, t), the
+  // that start in points [g n / G, (g+1) n / G) (found by searching the
+  // offsets; every environment has one start, so each goes to exactly one
+  // group), which keeps the two groups of a wave and all waves equally busy.  Group state: environment e (up to e_end), its range [b, t), the
   // current chunk start j0.
   const int64_t G = static_cast<int64_t>(gridDim.x) * NG, g = static_cast<int64_t>(blockIdx.x) * NG + grp;
-  auto first_env = [&](int64_t p) {  // first e in [0, n_env] with offsets[e] >= p
-    int64_t lo = 0, hi = P.n_env;
-    while (lo < hi) {
-      const int64_t mid = lo + (hi - lo) / 2;
-      if (P.offsets[mid] < p) lo = mid + 1;
-      else hi = mid;
-    }
-    return lo;
-  };
-  int64_t e = first_env(g * P.n / G);
-  const int64_t e_end = g + 1 == G ? P.n_env : first_env((g + 1) * P.n / G);
+  int64_t e = group_lower_bound(P.offsets, P.n_env, g * P.n / G, gl, grp * GS, GS);
+  const int64_t e_last = group_lower_bound(P.offsets, P.n_env, (g + 1) * P.n / G, gl, grp * GS, GS);
+  const int64_t e_end = g + 1 == G ? P.n_env : e_last;
   int64_t b = 0, t = 0, j0 = 0;
   auto next_env = [&]() {  // the group's next non-empty environment at or after e
     for (; e < e_end; ++e) {

@@ -88,14 +88,26 @@ __device__ __forceinline__ void hess_rows(const Point<T>& pt, T vx, T vy, T vz, 
   for (int l = la; l < lb; ++l) {
     q_row_rt<T, MM>(l, ez, pt.rxy2, cur);
     const int k0 = l * l + l;
-    const T fl = T(l), fl2 = T(l) * T(l + 2);
+    // normalised: H Y v = [h - l (g (u.v) + u (g.v)) - l Yt v + l(l+2) Yt u (u.v)] / r^2
+    //                   = [h - luv g - lu (g.v) - bv Yt] / r^2 per component,
+    // with the degree's luv = l (u.v), lu = l u, bv = l v - l(l+2) (u.v) u
+    T luv = T(0), lux = T(0), luy = T(0), luz = T(0), bx = T(0), by = T(0), bz = T(0);
+    if constexpr (NORM) {
+      const T fl = T(l), A = T(l) * T(l + 2) * uv;
+      luv = fl * uv;
+      lux = fl * ex;
+      luy = fl * ey;
+      luz = fl * ez;
+      bx = fl * vx - A * ex;
+      by = fl * vy - A * ey;
+      bz = fl * vz - A * ez;
+    }
     // Yt, g = grad Yt, gv = g.v, h = H(Yt) v of column k
     auto put = [&](int k, T Yt, T gx, T gy, T gz, T gv, T hx, T hy, T hz) {
       if constexpr (NORM) {
-        const T a = fl2 * Yt * uv;
-        hx = (hx - fl * (gx * uv + ex * gv) - fl * Yt * vx + a * ex) * ir2;
-        hy = (hy - fl * (gy * uv + ey * gv) - fl * Yt * vy + a * ey) * ir2;
-        hz = (hz - fl * (gz * uv + ez * gv) - fl * Yt * vz + a * ez) * ir2;
+        hx = (hx - luv * gx - lux * gv - bx * Yt) * ir2;
+        hy = (hy - luv * gy - luy * gv - by * Yt) * ir2;
+        hz = (hz - luv * gz - luz * gv - bz * Yt) * ir2;
       }
       if (has_row) {
         row[k] = hx;
