@@ -40,7 +40,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 METRIC = "points/s and HBM GB/s for Y+dY fwd+bwd, l_max=8 FP32; max err vs FP64 oracle"
 # The sources of the headline step's two kernels (their code, tables and
 # launch shapes): a change to any of them voids the committed byte counters.
-KERNEL_SOURCES = ["sph_device.hpp", "sph_coeffs.hpp", "sph_fwd.inl", "sph_fwd4.inl", "sph_bwd.inl",
+KERNEL_SOURCES = ["sph_device.hpp", "sph_coeffs.hpp", "sph_fwd.inl", "sph_fwd1.inl", "sph_fwd4.inl", "sph_bwd.inl",
                   "sph_instances.inl", "sph_kernels_derivs_f32_n1_m0.hip", "sph_kernels_bwd_f32.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_l8_f32.json")
 
@@ -322,6 +322,33 @@ def _time(fn, reps: int, warm: int = 3) -> float:
     return e0.elapsed_time(e1) * 1e-3 / reps
 
 
+def _time_graph(fn, reps: int, replays: int = 3) -> float:
+    """Mean GPU seconds per call of fn(): reps calls captured into one graph
+    and replayed, so the host's per-call work (argument checks, the
+    library's launch) does not leave the GPU idle between kernels.  For
+    kernels shorter than that host work; fn must not allocate or
+    synchronise."""
+    import torch
+    for _ in range(3):
+        fn()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(reps):
+            fn()
+    g.replay()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(replays):
+        g.replay()
+    e1.record(s)
+    torch.cuda.synchronize()
+    del g
+    return e0.elapsed_time(e1) * 1e-3 / (reps * replays)
+
+
 def extras(dev):
     """Secondary measurements of the other parts of the path (not the headline)."""
     import numpy as np
@@ -378,7 +405,11 @@ def extras(dev):
     # plain method, CPU-sized: N = 1000, float64, l_max = 4 (launch-bound)
     x1 = torch.as_tensor(standard_normal_points(1000, SEEDS["plain_cpu"]), dtype=torch.float64).to(dev)
     t1 = _time(lambda: sph.sph_compute_with_gradients(x1, 4, True), 50)
-    out["plain_l4_f64_1000"] = {"forward_s": t1, "points_per_s": 1000 / t1}
+    Y1 = torch.empty((1000, 25), dtype=torch.float64, device=dev)
+    dY1 = torch.empty((1000, 3, 25), dtype=torch.float64, device=dev)
+    t1g = _time_graph(lambda: sph.sph_compute_with_gradients(x1, 4, True, Y=Y1, dY=dY1), 50)
+    out["plain_l4_f64_1000"] = {"forward_s": t1, "points_per_s": 1000 / t1,
+                                "gpu_s_graph_replay": t1g, "note": "forward_s includes the host's work per call"}
     # precision workload: l_max = 32, N = 200 000 (unit sphere, near the poles,
     # radii 1e-6..1e3), float32 and float64; errors are checked by the tests
     from workloads import precision_stress_points
@@ -447,21 +478,34 @@ def extras(dev):
                         "backward_points_per_s": nb / tbw}
     out["radial_expansion_20k_envs_f32"] = exp
     # compile-time (unrolled, literal coefficients) against run-time-degree
-    # kernels at low l_max: the batched path on the same environments, Y and
-    # dY stored, one tile per block, each variant pinned
+    # kernels at low l_max, and the one-lane kernel: the batched path on the
+    # same environments, Y and dY stored, one tile per block, each variant
+    # pinned.  GPU time from graph replays: at l_max <= 2 a kernel is shorter
+    # than the host's work per call
     spec = {}
-    for Ls in range(1, 7):
+    for Ls in range(0, 7):
         Ks = (Ls + 1) ** 2
         o = {"Y": torch.empty((nb, Ks), device=dev), "dY": torch.empty((nb, 3, Ks), device=dev)}
         row = {}
-        for variant in ("default", "runtime_degree"):
+        # tile16: the compile-time quad-lane kernel on a 16-point tile; one_lane
+        # (l_max <= 3): one lane per point
+        for variant in ("default", "tile16", "runtime_degree") + (("one_lane",) if Ls <= 3 else ()):
             sph.sph_batched_set_config(Ls, True, torch.float32, True, False, variant, 0)
-            row[variant + "_s"] = _time(lambda: sph.sph_batched_compute(xc, oc, Ls, True, store_dY=True, out=o,
-                                                                              check=False), 20)
+            row[variant + "_s"] = _time_graph(lambda: sph.sph_batched_compute(xc, oc, Ls, True, store_dY=True,
+                                                                                    out=o, check=False), 20)
         row["GB_per_s_default"] = nb * 4 * (3 + 4 * Ks) / row["default_s"] / 1e9
         sph.sph_batched_set_config(Ls, True, torch.float32, True, False, "default", 0)
+        if Ls <= 3:  # with the fused backward as well
+            gYs = torch.as_tensor(standard_normal((nb, Ks), 1100 + Ls), dtype=torch.float32).to(dev)
+            o["grad_xyz"] = torch.empty((nb, 3), device=dev)
+            for variant in ("default", "tile16", "one_lane"):
+                sph.sph_batched_set_config(Ls, True, torch.float32, True, True, variant, 0)
+                row[variant + "_with_backward_s"] = _time_graph(
+                    lambda: sph.sph_batched_compute(xc, oc, Ls, True, store_dY=True, grad_Y=gYs, out=o,
+                                                    check=False), 20)
+            sph.sph_batched_set_config(Ls, True, torch.float32, True, True, "default", 0)
         spec[str(Ls)] = row
-    out["compile_time_vs_runtime_degree_f32"] = spec
+    out["low_lmax_variants_f32"] = spec
     return out
 
 

@@ -172,7 +172,8 @@ int32_t sph_compute_with_hessians(const void* xyz, int64_t n, int32_t l_max,
  * candidates are every kernel variant (the unrolled compile-time kernel on
  * its default tile, the same on a 16-point tile, the
  * run-time-degree kernel, the 16-point tile with its degrees split between
- * two waves) crossed with every persistent-grid size.
+ * two waves, and for l_max <= 3 the kernel with one lane per point) crossed
+ * with every persistent-grid size.
  *   xyz        in  [n_points,3]
  *   offsets    in  int64 [n_env+1], DEVICE memory
  *   n_env      number of environments (>= 0)
@@ -270,17 +271,17 @@ int32_t sph_batched_get_config(int32_t l_max, int32_t normalize, int32_t dtype,
  * sph_batched_set_config -- fixes the launch of a combination instead of
  * timing the candidates (for callers that need a known launch, e.g. before
  * capturing a graph, and for testing every variant).
- *   variant        0 default, 1 tile16, 2 runtime_degree, 3 degree_split
- *                  (as in sph_batched_get_config)
+ *   variant        0 default, 1 tile16, 2 runtime_degree, 3 degree_split,
+ *                  4 one_lane (as in sph_batched_get_config)
  *   blocks_per_cu  0 .. 64 (0: one tile per block)
  * Returns SPH_ERR_INVALID for an unknown combination, a variant that does
  * not exist for it, or an out of range blocks_per_cu; SPH_ERR_LMAX for l_max
  * out of range.  With dY or the backward: tile16 exists wherever the
  * default is unrolled (float l_max <= 12, double l_max <= 8),
  * runtime_degree for every l_max, degree_split for float 9 <= l_max <= 12,
- * double 4 <= l_max <= 8 and, without the backward, every larger l_max; a
- * variant may name the default kernel.  Values only: runtime_degree where
- * the default is unrolled.
+ * double 4 <= l_max <= 8 and, without the backward, every larger l_max;
+ * one_lane for l_max <= 3; a variant may name the default kernel.  Values
+ * only: runtime_degree where the default is unrolled.
  */
 int32_t sph_batched_set_config(int32_t l_max, int32_t normalize, int32_t dtype,
                                int32_t store_dY, int32_t with_backward,

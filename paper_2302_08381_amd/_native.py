@@ -387,7 +387,7 @@ def sph_batched_get_config(l_max: int, normalize: bool, dtype: torch.dtype, stor
     return buf.value.decode() if st == SPH_OK else None
 
 
-BATCHED_VARIANTS = {"default": 0, "tile16": 1, "runtime_degree": 2, "degree_split": 3}
+BATCHED_VARIANTS = {"default": 0, "tile16": 1, "runtime_degree": 2, "degree_split": 3, "one_lane": 4}
 
 
 def sph_batched_set_config(l_max: int, normalize: bool, dtype: torch.dtype, store_dY: bool,

@@ -188,6 +188,7 @@ const char* variant_name(int v) {
     case sph::kVarTile16: return "tile16";
     case sph::kVarRuntime: return "runtime_degree";
     case sph::kVarSplit: return "degree_split";
+    case sph::kVarLane: return "one_lane";
     default: return "?";
   }
 }

@@ -8,6 +8,7 @@
 #include "sph_bwd.inl"
 #include "sph_dbwd.inl"
 #include "sph_fwd.inl"
+#include "sph_fwd1.inl"
 #include "sph_fwd4.inl"
 
 #define SPH_CAT2(a, b) a##b
@@ -46,6 +47,10 @@ template <int MM>
 const void* split_rt_ptr() {
   return nullptr;
 }
+template <int LT>
+const void* lane_ptr() {
+  return nullptr;
+}
 #else
 constexpr bool kFused = SPH_MODE != kDerivStore;
 constexpr bool kStore = SPH_MODE != kDerivFused;
@@ -76,18 +81,29 @@ const void* split_rt_ptr() {
   else
     return nullptr;
 }
+// The one-lane kernel (l_max <= 3).
+template <int LT>
+const void* lane_ptr() {
+  if constexpr (LT <= kLaneMaxL)
+    return reinterpret_cast<const void*>(&k_fwd1<T, LT, kNorm, kFused, kStore>);
+  else
+    return nullptr;
+}
 #endif
 
 template <int... Ls>
-void fill_spec(const void** out, const void** alt, const void** split, std::integer_sequence<int, Ls...>) {
+void fill_spec(const void** out, const void** alt, const void** split, const void** lane,
+               std::integer_sequence<int, Ls...>) {
   if constexpr (kSpecMax >= 0) {
     const void* v[] = {kernel_ptr<Ls, Ls>()...};
     const void* a[] = {alt_ptr<Ls>()...};
     const void* d[] = {split_ptr<Ls>()...};
+    const void* o[] = {lane_ptr<Ls>()...};
     for (size_t i = 0; i < sizeof...(Ls); ++i) {
       out[i] = v[i];
       alt[i] = a[i];
       split[i] = d[i];
+      lane[i] = o[i];
     }
   }
 }
@@ -106,11 +122,12 @@ struct Tables {
   const void* spec[kSpecSlots] = {};
   const void* spec_alt[kSpecSlots] = {};
   const void* spec_split[kSpecSlots] = {};
+  const void* spec_lane[kSpecSlots] = {};
   const void* buckets[kNumBuckets] = {};
   const void* buckets_split[kNumBuckets] = {};
   Tables() {
     if constexpr (kSpecMax >= 0)
-      fill_spec(spec, spec_alt, spec_split, std::make_integer_sequence<int, kSpecSlots>{});
+      fill_spec(spec, spec_alt, spec_split, spec_lane, std::make_integer_sequence<int, kSpecSlots>{});
     fill_buckets(buckets, buckets_split, Buckets{});
   }
 };
@@ -171,6 +188,15 @@ const void* pick(int L, int variant, int& nw, int& ds, bool quad) {
   ds = 1;
   switch (variant) {
     case kVarDefault:
+      // l_max <= 1: one lane per point.  GPU time on 1.36 M points (graph
+      // replays, one tile per block), against the quad-lane tile: float
+      // Y+dY 7.2 vs 17.2 us (l_max 0), 15.6 vs 19.7 us (1); with the fused
+      // backward 13.8 vs 24.8 and 25.5 vs 32.8 us; double within 5 % or
+      // faster.  At l_max 2 and 3 the two are even without the backward.
+      if (ct && quad && L <= 1 && tables().spec_lane[L] != nullptr) {
+        nw = 0;
+        return tables().spec_lane[L];
+      }
       if (ct && quad && tables().spec_split[L] != nullptr && split_by_default(L)) {
         ds = 2;
         return tables().spec_split[L];
@@ -190,6 +216,9 @@ const void* pick(int L, int variant, int& nw, int& ds, bool quad) {
     case kVarSplit:
       ds = 2;
       return ct ? tables().spec_split[L] : tables().buckets_split[bucket_index(L)];
+    case kVarLane:  // nw = 0 marks the one-lane kernel
+      nw = 0;
+      return quad && ct ? tables().spec_lane[L] : nullptr;
     default:
       return nullptr;
   }
@@ -215,6 +244,8 @@ KernelInfo SPH_CAT(SPH_CAT(SPH_CAT(SPH_CAT(SPH_CAT(fwd_derivs_, SPH_SUFFIX), _n)
   const void* fn = pick(L, variant, nw, ds, true);
   if (fn == nullptr) return KernelInfo{nullptr, 0, 0, 0, 0};
   const size_t row = sizeof(T) * static_cast<size_t>(tile_stride<T>(L, kQuadBudget<T>));
+  if (nw == 0)  // one lane per point: 4 * 64 rows, plus 64 gY rows when fused
+    return KernelInfo{fn, row * static_cast<size_t>(4 * kWave), row * static_cast<size_t>(5 * kWave), kWave, kWave};
   const int pts = kQuadWavePoints * nw, thr = kWave * nw * ds;
   // fused: the upstream-gradient tile, and the split kernel's partial sums
   const size_t fused = row * static_cast<size_t>(5 * pts) + (ds == 2 ? sizeof(T) * kWave : 0);

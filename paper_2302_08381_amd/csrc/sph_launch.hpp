@@ -140,11 +140,13 @@ struct KernelInfo {
 // Per element type (suffix f32 / f64) and normalisation; fn == nullptr when
 // the arguments are out of range or the variant does not exist for l_max.
 //   values:      Y only (one lane per point, 64-point tiles, 64 threads)
-//   derivatives: four lanes per point, 32- or 16-point tiles; mode
+//   derivatives: four lanes per point, 32- or 16-point tiles (one lane per point
+//                and 64-point tiles for the one-lane kernel); mode
 //                kDerivStore (Y and dY), kDerivFusedStore (Y, dY and the
 //                fused backward), kDerivFused (Y and the fused backward)
 // Variants (the batched autotuner's candidates; two may name one kernel):
-//   kVarDefault  the compile-time (unrolled) kernel where one exists, on its
+//   kVarDefault  the one-lane kernel for l_max <= 1; else the compile-time
+//                (unrolled) kernel where one exists, on its
 //                default tile (32 points on two waves for float l_max <= 8,
 //                the degree-split tile where that measured faster, else 16
 //                points on one wave), else the run-time-degree kernel (with
@@ -155,8 +157,9 @@ struct KernelInfo {
 //   kVarSplit    a degree-split kernel: the compile-time one (float l_max
 //                9..12, double 4..8) or the run-time-degree one (larger
 //                l_max, no fused backward)
+//   kVarLane     l_max <= 3: one lane per point, 64-point one-wave tiles
 enum DerivMode { kDerivStore = 0, kDerivFusedStore = 1, kDerivFused = 2, kNumDerivModes = 3 };
-enum FwdVariant { kVarDefault = 0, kVarTile16 = 1, kVarRuntime = 2, kVarSplit = 3, kNumFwdVariants = 4 };
+enum FwdVariant { kVarDefault = 0, kVarTile16 = 1, kVarRuntime = 2, kVarSplit = 3, kVarLane = 4, kNumFwdVariants = 5 };
 KernelInfo fwd_values_f32_n0(int L, int variant);
 KernelInfo fwd_values_f32_n1(int L, int variant);
 KernelInfo fwd_values_f64_n0(int L, int variant);
