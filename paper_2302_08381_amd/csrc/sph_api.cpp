@@ -525,7 +525,8 @@ int32_t sph_radial_expansion_backward(const void* xyz, const int64_t* offsets, i
   if (ki.lds_bytes > 160 * 1024) return fail(SPH_ERR_INVALID, "l_max and n_max need more LDS than one block has");
   hipError_t e = ensure_lds(ki.fn, ki.lds_bytes);
   if (e != hipSuccess) return device_fail(e, "hipFuncSetAttribute");
-  sph::ExpandBwdParams p{xyz, R, offsets, n_env, n_points, l_max, n_max, grad_c, grad_xyz, grad_R, status};
+  sph::ExpandBwdParams p{xyz, R, offsets, n_env, n_points, l_max, n_max, grad_c, grad_xyz, grad_R, status,
+                         ki.slices};
   // a resident grid of one-wave blocks, each block's lane groups
   // (tile_points of them) walking their own environments
   const int64_t resident = static_cast<int64_t>(num_cus()) * resident_per_cu(ki.fn, ki.block, ki.lds_bytes);

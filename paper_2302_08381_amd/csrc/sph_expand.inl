@@ -351,7 +351,10 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandParams P) {
 //            they are read;
 //   SRC = 1: global memory as 16-byte vectors (channels = NPC, 16-byte
 //            aligned), in one of two register buffers, the next degree's
-//            loads issued before this degree's arithmetic;
+//            loads issued before this degree's arithmetic.  Plain loads: a
+//            lane reads its 16-byte pieces of a row over several degrees,
+//            and with the nontemporal hint the lines left L2 between them
+//            and were fetched again (20-30 % slower);
 //   SRC = 2: global memory element by element.
 template <typename T, int MM, bool NORM, int NPC, int SRC>
 __device__ __forceinline__ void expand_bwd_point(const T* __restrict__ xyz, const T* __restrict__ R,
@@ -396,13 +399,22 @@ __device__ __forceinline__ void expand_bwd_point(const T* __restrict__ xyz, cons
   V ra[NV], rb[NV];
   auto load_r = [&](int l, V (&dst)[NV]) {
 #pragma unroll
-    for (int h = 0; h < NV; ++h) dst[h] = __builtin_nontemporal_load(reinterpret_cast<const V*>(Rj + l * NPC) + h);
+    for (int h = 0; h < NV; ++h) dst[h] = reinterpret_cast<const V*>(Rj + l * NPC)[h];
   };
   // degree l; SRC = 1: radial values in rc, the next degree's loads issued
   // into rx first (unconditionally: the last degree loads itself again, so
   // the wait analysis sees one path)
   auto degree = [&](int l, const V (&rc)[NV], V (&rx)[NV]) {
     if constexpr (SRC == 1) load_r(l < L ? l + 1 : l, rx);
+    // the degree's derivative coefficients, fetched together before any
+    // column: scalar loads share their wait counter with LDS reads, so a
+    // fetch next to each column would drain every G read in flight
+    T kg[MM + 1], kz[MM + 1];
+#pragma unroll
+    for (int m = 0; m <= MM; ++m) {
+      kg[m] = C.gxy[l][m];
+      kz[m] = C.gz[l][m];
+    }
     q_row_rt<T, MM>(l, ez, pt.rxy2, cur);
     T r[NPC], acc[NPC];
     if constexpr (SRC == 0) {
@@ -470,8 +482,8 @@ __device__ __forceinline__ void expand_bwd_point(const T* __restrict__ xyz, cons
         ms = T(m) * s1;
       }
       const T q = cur[m];
-      const T Tm = (m <= l - 2) ? C.gxy[l][m] * prev[m + 1] : T(0);
-      const T Cz = (m <= l - 1) ? C.gz[l][m] * prev[m] : T(0);
+      const T Tm = (m <= l - 2) ? kg[m] * prev[m + 1] : T(0);
+      const T Cz = (m <= l - 1) ? kz[m] * prev[m] : T(0);
       const T xt = ex * Tm, yt = ey * Tm;
       if (m == 0) {
         col(k0, q * kIS2, xt * kIS2, yt * kIS2, Cz * kIS2);
@@ -611,21 +623,23 @@ __device__ __forceinline__ void expand_tile_out(const T* __restrict__ sR, int RS
 //                     gY[j, k] = sum_n G[e, n, k] R[j, l(k), n]
 // One lane per point; neither Y nor dY is stored.  A block is one wave split
 // into 64 / GS groups of GS lanes, each walking its own run of environments
-// (an even share of the points) in chunks of GS points, so a wave's lanes
-// stay busy across environments of any size.  Each
-// group keeps its environment's G in its own LDS slice ([k][channel], read
-// as 16-byte vectors, one address per group).  Per point, one pass per
-// degree forms every value and derivative of the row at once (Eq. iter-deri
-// with the order-m factors tabulated once per point), contracts it with G
-// and the point's radial values of that degree, and produces the degree's
-// grad_R.  STAGE: each chunk's radial rows arrive in an LDS tile by
-// coalesced 16-byte copies and its grad_R leaves the same way, so HBM sees
-// each byte once; otherwise every lane reads and writes its own rows.  NPC:
-// channels padded to a multiple of 4 (8 or 16).
+// (an even share of the points) in chunks of GS consecutive points.  A chunk
+// may span the end of one environment and the start of the next: the group
+// keeps the G of both in two LDS slices ([k][channel], read as 16-byte
+// vectors) and each lane reads the slice of its own point's environment.
+// Chunks that stopped at every environment's end would leave a fifth of the
+// lanes idle on environments of 8..128 points (a third with 64 lanes); where
+// two slices would not fit one block's LDS (P.slices = 1) they do stop.  Per
+// point, one pass per degree forms every value and derivative of the row at
+// once (Eq. iter-deri with the order-m factors tabulated once per point),
+// contracts it with G and the point's radial values of that degree, and
+// produces the degree's grad_R.  STAGE: each chunk's radial rows arrive in
+// an LDS tile by coalesced 16-byte copies and its grad_R leaves the same
+// way; otherwise every lane reads and writes its own rows.  NPC: channels
+// padded to a multiple of 4 (8 or 16).
 template <typename T, int MM, bool NORM, int NPC, int GS, bool STAGE>
 __global__ __launch_bounds__(kWave) void k_expand_bwd(ExpandBwdParams P) {
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int W = Vec16<T>::n;
   constexpr int NG = kWave / GS;
   const int lane = threadIdx.x;
   const int grp = lane / GS, gl = lane % GS;
@@ -633,9 +647,11 @@ __global__ __launch_bounds__(kWave) void k_expand_bwd(ExpandBwdParams P) {
   const int K = (L + 1) * (L + 1);
   const int NM = P.n_max;
   const int RS = expand_bwd_row_stride<T>(L, NPC);
+  const size_t slice = static_cast<size_t>(K) * NPC;
+  const int nsl = P.slices;  // 2: chunks may span two environments
   T* sG = reinterpret_cast<T*>(smem) +
-          static_cast<size_t>(grp) * (static_cast<size_t>(K) * NPC + (STAGE ? static_cast<size_t>(GS) * RS : 0));
-  T* sR = sG + static_cast<size_t>(K) * NPC;
+          static_cast<size_t>(grp) * (nsl * slice + (STAGE ? static_cast<size_t>(GS) * RS : 0));
+  T* sR = sG + nsl * slice;
   const T* xyz = static_cast<const T*>(P.xyz);
   const T* R = static_cast<const T*>(P.R);
   const T* gc = static_cast<const T*>(P.gc);
@@ -644,7 +660,6 @@ __global__ __launch_bounds__(kWave) void k_expand_bwd(ExpandBwdParams P) {
   // radial rows as whole 16-byte vectors: every padded channel present and
   // both radial arrays 16-byte aligned (uniform)
   const bool vec = NM == NPC && aligned16(R) && (gR == nullptr || aligned16(gR));
-  (void)W;
 
   if (P.status != nullptr && blockIdx.x == 0) {
     bool ok = true;
@@ -657,32 +672,61 @@ __global__ __launch_bounds__(kWave) void k_expand_bwd(ExpandBwdParams P) {
   // The groups split the points evenly: group g of G takes the environments
   // that start in points [g n / G, (g+1) n / G) (found by searching the
   // offsets; every environment has one start, so each goes to exactly one
-  // group), which keeps the two groups of a wave and all waves equally busy.  Group state: environment e (up to e_end), its range [b, t), the
-  // current chunk start j0.
+  // group), which keeps the two groups of a wave and all waves equally busy.
+  // Group state: environment e, its range [b, t), the chunk start j0
+  // (b <= j0 < t), and which environment each G slice holds.
   const int64_t G = static_cast<int64_t>(gridDim.x) * NG, g = static_cast<int64_t>(blockIdx.x) * NG + grp;
   int64_t e = group_lower_bound(P.offsets, P.n_env, g * P.n / G, gl, grp * GS, GS);
   const int64_t e_last = group_lower_bound(P.offsets, P.n_env, (g + 1) * P.n / G, gl, grp * GS, GS);
   const int64_t e_end = g + 1 == G ? P.n_env : e_last;
   int64_t b = 0, t = 0, j0 = 0;
-  auto next_env = [&]() {  // the group's next non-empty environment at or after e
-    for (; e < e_end; ++e) {
-      env_range(P.offsets, e, P.n, b, t);
-      if (t > b) break;
+  // first non-empty environment at or after ee (e_end if none), its range
+  auto next_nonempty = [&](int64_t ee, int64_t& bb, int64_t& tt) {
+    for (; ee < e_end; ++ee) {
+      env_range(P.offsets, ee, P.n, bb, tt);
+      if (tt > bb) break;
     }
-    j0 = b;
+    return ee;
   };
-  next_env();
-  bool load_g = true;
+  e = next_nonempty(e, b, t);
+  j0 = b;
+  int se = 0;                         // the slice of environment e
+  int64_t in_cur = -1, in_oth = -1;  // environments whose G slices se, 1 - se hold
+  auto load_slice = [&](int sl, int64_t env) {
+    const T* ge = gc + env * NM * K;
+    T* dst = sG + sl * slice;
+    for (int i = gl; i < NPC * K; i += GS) {
+      const int n = i / K;
+      const int k = i - n * K;
+      dst[k * NPC + n] = n < NM ? ge[i] : T(0);
+    }
+  };
   while (__any(e < e_end)) {
     const bool active = e < e_end;
-    const int cnt = active ? static_cast<int>(t - j0 < GS ? t - j0 : GS) : 0;
-    __syncthreads();  // every read of the previous tiles of this wave is done
-    if (active && load_g) {
-      const T* ge = gc + e * NM * K;
-      for (int i = gl; i < NPC * K; i += GS) {
-        const int n = i / K;
-        const int k = i - n * K;
-        sG[k * NPC + n] = n < NM ? ge[i] : T(0);
+    // the chunk: GS points from j0, running into the next non-empty
+    // environment e2 when e ends first and e2 starts where e ends
+    int64_t b2 = 0, t2 = 0, e2 = e_end;
+    int cnt = 0;
+    if (active) {
+      cnt = static_cast<int>(t - j0 < GS ? t - j0 : GS);
+      if (cnt < GS && nsl == 2) {
+        e2 = next_nonempty(e + 1, b2, t2);
+        if (e2 < e_end && b2 == t)
+          cnt = static_cast<int>(t2 - j0 < GS ? t2 - j0 : GS);
+        else
+          e2 = e_end;
+      }
+    }
+    const bool span = e2 < e_end;
+    __syncthreads();  // every read of the previous chunk's slices and tile is done
+    if (active) {
+      if (in_cur != e) {
+        load_slice(se, e);
+        in_cur = e;
+      }
+      if (span && in_oth != e2) {
+        load_slice(1 - se, e2);
+        in_oth = e2;
       }
     }
     if constexpr (STAGE) {
@@ -697,12 +741,13 @@ __global__ __launch_bounds__(kWave) void k_expand_bwd(ExpandBwdParams P) {
     __syncthreads();
     const int64_t j = j0 + gl;
     if (active && gl < cnt) {
+      const T* sGj = sG + (j < t ? se : 1 - se) * slice;
       if constexpr (STAGE)
-        expand_bwd_point<T, MM, NORM, NPC, 0>(xyz, R, sG, sR + gl * RS, gxyz, gR, j, L, NM);
+        expand_bwd_point<T, MM, NORM, NPC, 0>(xyz, R, sGj, sR + gl * RS, gxyz, gR, j, L, NM);
       else if (vec)
-        expand_bwd_point<T, MM, NORM, NPC, 1>(xyz, R, sG, nullptr, gxyz, gR, j, L, NM);
+        expand_bwd_point<T, MM, NORM, NPC, 1>(xyz, R, sGj, nullptr, gxyz, gR, j, L, NM);
       else
-        expand_bwd_point<T, MM, NORM, NPC, 2>(xyz, R, sG, nullptr, gxyz, gR, j, L, NM);
+        expand_bwd_point<T, MM, NORM, NPC, 2>(xyz, R, sGj, nullptr, gxyz, gR, j, L, NM);
     }
     if constexpr (STAGE) {
       if (gR != nullptr) {
@@ -716,14 +761,21 @@ __global__ __launch_bounds__(kWave) void k_expand_bwd(ExpandBwdParams P) {
         }
       }
     }
-    // advance the group: next chunk, else the next environment
-    load_g = false;
+    // advance the group past the chunk
     if (active) {
-      j0 += GS;
-      if (j0 >= t) {
-        ++e;
-        next_env();
-        load_g = true;
+      j0 += cnt;
+      if (span) {  // the chunk ended inside e2 (or at its end): e2 becomes e
+        e = e2;
+        b = b2;
+        t = t2;
+        se = 1 - se;
+        const int64_t h = in_cur;
+        in_cur = in_oth;
+        in_oth = h;
+      }
+      if (j0 >= t) {  // e done: the next non-empty environment
+        e = next_nonempty(e + 1, b, t);
+        j0 = b;
       }
     }
   }

@@ -104,6 +104,7 @@ struct ExpandBwdParams {
   void* gxyz;              // [n,3] or null
   void* gR;                // [n, L+1, n_max] or null
   int32_t* status;         // device status word or null
+  int32_t slices;          // G slices per lane group: 2 (chunks may span two environments) or 1
 };
 // Row stride (elements) of the backward's LDS radial tile: (L+1) * np
 // channels, padded so that a row spans an odd number of 16-byte vectors
@@ -115,12 +116,13 @@ __host__ __device__ constexpr int expand_bwd_row_stride(int L, int np) {
   return (s / W) % 2 == 1 ? s : s + W;
 }
 // LDS of one backward block (one wave in groups of gs lanes): each group's
-// environment gradient G as [K][np] and, when staged, its radial tile of gs
-// rows.
+// environment gradients G as [K][np], `slices` of them (two where a chunk
+// may span two environments), and, when staged, its radial tile of gs rows.
 template <typename T>
-__host__ __device__ constexpr size_t expand_bwd_lds_bytes(int L, int np, int gs, bool stage) {
+__host__ __device__ constexpr size_t expand_bwd_lds_bytes(int L, int np, int gs, bool stage, int slices = 2) {
   const int K = (L + 1) * (L + 1);
-  const size_t per = static_cast<size_t>(K) * np + (stage ? static_cast<size_t>(gs) * expand_bwd_row_stride<T>(L, np) : 0);
+  const size_t per = static_cast<size_t>(slices) * K * np +
+                     (stage ? static_cast<size_t>(gs) * expand_bwd_row_stride<T>(L, np) : 0);
   return sizeof(T) * static_cast<size_t>(64 / gs) * per;
 }
 
@@ -135,6 +137,7 @@ struct KernelInfo {
   int tile_points;
   int block;
   int blocks_per_cu = 0;  // plain calls: 1: a resident grid (occupancy x CUs) loops over tiles; 0: one tile per block
+  int slices = 0;         // the expansion backward: G slices per lane group
 };
 
 // Per element type (suffix f32 / f64) and normalisation; fn == nullptr when
@@ -193,7 +196,8 @@ KernelInfo hess_info_f64(int L, int normalize);
 KernelInfo expand_info_f32(int L, int normalize, int n_max);
 KernelInfo expand_info_f64(int L, int normalize, int n_max);
 // Its backward: channels padded to 8 or 16 (n_max <= 16); tile_points holds
-// the padded channel count.
+// the lane groups per block, slices the G slices per group (two unless two
+// do not fit one block's LDS).
 KernelInfo expand_bwd_info_f32(int L, int normalize, int n_max);
 KernelInfo expand_bwd_info_f64(int L, int normalize, int n_max);
 

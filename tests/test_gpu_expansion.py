@@ -194,9 +194,7 @@ def _check_backward(gx, gR, pts, offs, R, G, l_max, normalize, dt, label=""):
 @pytest.mark.parametrize("dt", [torch.float32, torch.float64])
 @pytest.mark.parametrize("l_max,n_max,normalize", [
     (0, 1, True), (2, 3, False), (4, 8, True), (8, 8, True), (8, 5, False), (8, 16, True), (11, 4, True),
-    (20, 9, True),
-    # one 64-lane group per wave (two groups' LDS would pass 64 KiB)
-    (28, 12, True)])
+    (20, 9, True), (28, 12, True)])
 def test_expansion_backward_matches_oracle(dt, l_max, n_max, normalize):
     import paper_2302_08381_amd as sph
     print(f"expansion backward {dt} l_max={l_max} n_max={n_max} normalize={normalize}", flush=True)
@@ -217,6 +215,33 @@ def test_expansion_backward_matches_oracle(dt, l_max, n_max, normalize):
     assert torch.equal(only_x, gx)
     _check_backward(gx, gR, host_points(xyz), offs, Rt.cpu().double().numpy(), Gt.cpu().double().numpy(),
                     l_max, normalize, dt, f"{dt} L={l_max} n={n_max}")
+
+
+@pytest.mark.parametrize("dt,l_max", [(torch.float32, 3), (torch.float32, 9), (torch.float64, 4),
+                                        (torch.float64, 6)])
+def test_expansion_backward_chunks_across_environments(dt, l_max):
+    """20 000 environments of 0..8 points (a tenth empty): every group of
+    lanes walks several environments, and its chunks run across environment
+    ends, across empty environments and stop exactly at an end.  Staged
+    (float32 l_max 3, float64 l_max 4) and direct (float32 l_max 9, float64
+    l_max 6) radial rows."""
+    import paper_2302_08381_amd as sph
+    print(f"expansion backward across environments {dt} l_max={l_max}", flush=True)
+    rng = np.random.default_rng(900 + l_max)
+    counts = rng.integers(1, 9, 20_000)
+    counts[rng.random(counts.size) < 0.1] = 0
+    n_max = 8
+    pts, offs, R = _case(counts, l_max, n_max, 910 + l_max)
+    xyz = to_dev(pts, dt)
+    Rt = to_dev(R, dt)
+    Gt = to_dev(standard_normal((offs.size - 1, n_max, (l_max + 1) ** 2), 920 + l_max), dt)
+    o = torch.as_tensor(offs, device="cuda")
+    gx, gR = sph.sph_radial_expansion_backward(xyz, o, Rt, Gt, l_max, True)
+    only_x, _ = sph.sph_radial_expansion_backward(xyz, o, Rt, Gt, l_max, True, want_grad_R=False)
+    torch.cuda.synchronize()
+    assert torch.equal(only_x, gx)
+    _check_backward(gx, gR, host_points(xyz), offs, Rt.cpu().double().numpy(), Gt.cpu().double().numpy(),
+                    l_max, True, dt, f"{dt} L={l_max} across environments")
 
 
 def test_expansion_backward_through_autograd_matches_torch():
