@@ -111,8 +111,10 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandParams P) {
   // The blocks split the points evenly: block g of G takes the environments
   // that start in points [g n / G, (g+1) n / G) (found by searching the
   // offsets; every environment has one start, so each goes to exactly one
-  // block; see kEven for small l_max).  The block walks its chunks (points j0 .. j0 + JC of each
-  // environment) as a pipeline: the coordinates and the first radial batch
+  // block; see kEven for small l_max).  The block walks its chunks (up to
+  // JC consecutive points, within one environment or across the end of one
+  // into the next, see shape) as a pipeline: the coordinates and the first
+  // radial batch
   // of chunk i + 1 are loaded into registers while chunk i's harmonics are
   // computed and contracted.  Indices past a chunk load its last element
   // again (in bounds, never stored), which keeps the loads unconditional.
@@ -133,14 +135,9 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandParams P) {
     e = __shfl(bound, 0);
     e_end = g + 1 == G ? P.n_env : __shfl(bound, 32);
   }
-  // moves (e, b, t, j0) to the next chunk at or after environment e (j0 =
-  // start of e when fresh); false when the block has no chunk left
-  auto seek = [&](bool fresh) {
-    if (!fresh) {
-      j0 += JC;
-      if (j0 < t) return true;
-      e += estep;
-    }
+  // the first non-empty environment at or after e (j0 = its start); false
+  // when the block has none left
+  auto scan = [&]() {
     for (; e < e_end; e += estep) {
       env_range(P.offsets, e, P.n, b, t);
       j0 = b;
@@ -150,10 +147,49 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandParams P) {
     }
     return false;
   };
+  // The chunk at (e, j0): cnt points from j0.  With the even split, a chunk
+  // that reaches the end of e runs on into environment e + 1 when that one
+  // starts there and is not empty (span; e's points are the first cut,
+  // e + 1 ends at t2): chunks that stopped at every environment's end were
+  // two thirds full on environments of 8..128 points at 64-point chunks.
+  auto shape = [&](int& cnt, int& cut, bool& span, int64_t& t2) {
+    cnt = static_cast<int>(t - j0 < JC ? t - j0 : JC);
+    cut = cnt;
+    span = false;
+    if constexpr (kEven) {
+      if (cnt < JC && e + 1 < e_end) {
+        int64_t b2 = 0, tn = 0;
+        env_range(P.offsets, e + 1, P.n, b2, tn);
+        if (b2 == t && tn > b2) {
+          span = true;
+          t2 = tn;
+          cnt = static_cast<int>(tn - j0 < JC ? tn - j0 : JC);
+        }
+      }
+    }
+  };
+  // moves the walk past the chunk it has just done; false when the block
+  // has no chunk left
+  auto advance = [&](int cnt, bool span, int64_t t2) {
+    if (span) {  // now inside e + 1 (the even split walks with estep = 1)
+      ++e;
+      b = t;
+      t = t2;
+      j0 += cnt;
+    } else {
+      j0 += JC;
+    }
+    if (j0 < t) return true;
+    e += estep;
+    return scan();
+  };
   T px = T(0), py = T(0), pz = T(0);
   T rb[RB];
   auto issue = [&]() {  // coordinates and first radial batch of chunk (e, j0)
-    const int cnt = static_cast<int>(t - j0 < JC ? t - j0 : JC);
+    int cnt = 0, cut = 0;
+    bool span = false;
+    int64_t t2 = 0;
+    shape(cnt, cut, span, t2);
     const int64_t jp = j0 + (tid % JC < cnt ? tid % JC : cnt - 1);
     px = xyz[jp * 3 + 0];
     py = xyz[jp * 3 + 1];
@@ -177,13 +213,17 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandParams P) {
     }
   };
 
-  bool more = seek(true);
+  bool more = scan();
   if (more) issue();
   while (more) {
-    const int cnt = static_cast<int>(t - j0 < JC ? t - j0 : JC);
+    int cnt = 0, cut = 0;
+    bool span = false;
+    int64_t ct2 = 0;
+    shape(cnt, cut, span, ct2);
     const int nrv = cnt * (L + 1) * NM;
     const int64_t cb = b, ct = t, c0 = j0;
     T* ce = c + e * NM * K;
+    T* ce2 = span ? ce + NM * K : nullptr;  // environment e + 1
     // this chunk's loads: one wait for all of them
     __builtin_amdgcn_s_waitcnt(kWaitVmem0);
     rstore(0, nrv);
@@ -208,7 +248,7 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandParams P) {
       }
     }
     // the next chunk's loads fly during this chunk's arithmetic
-    more = seek(false);
+    more = advance(cnt, span, ct2);
     if (more) issue();
     // The chunk's harmonics: point tid % JC, degrees [la, lb) of part
     // tid / JC.  A chunk narrower than the block splits each point's degrees
@@ -319,24 +359,44 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandParams P) {
         constexpr int W = Vec16<T>::n;
         const T* yc = sY + k;
         const T* rc = sR + l * NP + g * ACC;  // 16-byte aligned (NP, ACC multiples of 4)
+        auto sum = [&](int ja, int jb) {
 #pragma unroll 4
-        for (int j = 0; j < cnt; ++j) {
-          const T yv = yc[j * SY];
-          const V* r = reinterpret_cast<const V*>(rc + j * RS);
+          for (int j = ja; j < jb; ++j) {
+            const T yv = yc[j * SY];
+            const V* r = reinterpret_cast<const V*>(rc + j * RS);
 #pragma unroll
-          for (int h = 0; h < ACC / W; ++h) {
-            const V rv = r[h];
+            for (int h = 0; h < ACC / W; ++h) {
+              const V rv = r[h];
 #pragma unroll
-            for (int u = 0; u < W; ++u) a[h * W + u] += rv[u] * yv;
+              for (int u = 0; u < W; ++u) a[h * W + u] += rv[u] * yv;
+            }
           }
-        }
-        if (last) {
+        };
+        auto to_c = [&](T* cc) {
 #pragma unroll
           for (int u = 0; u < ACC; ++u)
-            if (g * ACC + u < NM) ce[(g * ACC + u) * K + k] = a[u];
-        } else {
+            if (g * ACC + u < NM) cc[(g * ACC + u) * K + k] = a[u];
+        };
+        auto to_partial = [&]() {
 #pragma unroll
           for (int u = 0; u < ACC; ++u) sC[(g * ACC + u) * K + k] = a[u];
+        };
+        sum(0, cut);
+        if (!span) {
+          if (last)
+            to_c(ce);
+          else
+            to_partial();
+        } else {
+          // e ends in this chunk; e + 1 starts at point cut
+          to_c(ce);
+#pragma unroll
+          for (int u = 0; u < ACC; ++u) a[u] = T(0);
+          sum(cut, cnt);
+          if (c0 + cnt >= ct2)
+            to_c(ce2);
+          else
+            to_partial();
         }
       }
     }

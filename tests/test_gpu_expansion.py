@@ -75,6 +75,41 @@ def test_expansion_matches_oracle(dt, l_max, n_max, normalize):
            f"{dt} L={l_max} n={n_max}")
 
 
+@pytest.mark.parametrize("dt,l_max,n_max", [(torch.float32, 5, 8), (torch.float32, 8, 8), (torch.float32, 12, 3),
+                                              (torch.float64, 6, 8)])
+def test_expansion_chunks_across_environments(dt, l_max, n_max):
+    """20 000 environments of 0..8 points (a tenth empty) and a few of 150:
+    every block walks many environments, its chunks run from the end of one
+    environment into the next (not across empty ones), and a chunk that
+    starts a long environment leaves partial sums for the next."""
+    import paper_2302_08381_amd as sph
+    print(f"expansion across environments {dt} l_max={l_max} n_max={n_max}", flush=True)
+    rng = np.random.default_rng(940 + l_max)
+    counts = rng.integers(1, 9, 20_000)
+    counts[rng.random(counts.size) < 0.1] = 0
+    counts[::997] = 150
+    pts, offs, R = _case(counts, l_max, n_max, 950 + l_max)
+    xyz = to_dev(pts, dt)
+    Rt = to_dev(R, dt)
+    c = sph.sph_radial_expansion(xyz, torch.as_tensor(offs, device="cuda"), Rt, l_max, True)
+    torch.cuda.synchronize()
+    hp, Rh = host_points(xyz), Rt.cpu().double().numpy()
+    got = c.cpu().double().numpy()
+    ref = np.asarray(oracle.radial_expansion(hp, offs, Rh, l_max, True), float)
+    # the bound of _check, per environment at once
+    s, _, _ = oracle.component_scales(hp, l_max, True)
+    lk = np.array([l for l in range(l_max + 1) for _ in range(2 * l + 1)])
+    cnts = np.diff(offs)
+    nz = cnts > 0
+    scale = np.zeros((cnts.size, (l_max + 1) ** 2, n_max))
+    scale[nz] = np.add.reduceat(np.abs(Rh[:, lk, :]) * s[:, :, None], offs[:-1][nz], axis=0)
+    scale = scale.transpose(0, 2, 1) + 1e-300
+    tol = (TOL[dt] + cnts * EPS[dt])[:, None, None]
+    assert np.all(got[~nz] == 0)
+    err = np.abs(got - ref) / scale
+    assert np.isfinite(got).all() and np.all(err <= tol), float((err / tol).max())
+
+
 @pytest.mark.parametrize("l_max,n_max", [(20, 4), (32, 8)])
 def test_expansion_large_degree_small_chunks(l_max, n_max):
     """Large K: 8- to 32-point chunks, so long environments add many partial
