@@ -157,6 +157,47 @@ int32_t sph_compute_with_hessians(const void* xyz, int64_t n, int32_t l_max,
                                   void* dY, void* d2Y, void* stream);
 
 /*
+ * e3nn's conventions (Sec. III.B: the method's library provides wrappers
+ * that follow them).  e3nn's real harmonics take y as the polar axis: they
+ * are this library's harmonics evaluated at the cyclically permuted point
+ * (z, x, y) (so that degree 1 is proportional to (x, y, z), in that order),
+ * times a per-degree normalisation factor, with the derivatives taken along
+ * the caller's axes.  A call of e3nn's convention is
+ *   sph_e3nn_coordinates(xyz -> xyz_p), sph_compute_with_gradients(xyz_p ->
+ *   Y, dY), sph_e3nn_convert(Y, dY),
+ * all on one stream; the backward of the result is sph_backward with the
+ * converted dY.
+ *
+ * sph_e3nn_coordinates -- xyz_p[i] = (xyz[i,2], xyz[i,0], xyz[i,1]).
+ *   xyz        in  [n,3]
+ *   xyz_p      out [n,3]; may be xyz itself (each point is read before it is
+ *              written), must not overlap it otherwise
+ * Errors: SPH_ERR_NULL for a NULL buffer with n > 0; SPH_ERR_INVALID for
+ * n < 0, a bad dtype or a partial overlap.
+ */
+int32_t sph_e3nn_coordinates(const void* xyz, int64_t n, int32_t dtype,
+                             void* xyz_p, void* stream);
+
+/*
+ * sph_e3nn_convert -- in place, turns Y[n,K] (and dY[n,3,K]) computed at
+ * sph_e3nn_coordinates' points into e3nn's convention:
+ *   Y[i,k] *= c_l,  (dY[i,0,k], dY[i,1,k], dY[i,2,k]) <-
+ *                   c_l (dY[i,1,k], dY[i,2,k], dY[i,0,k])   (k of degree l)
+ * (the derivatives along the permuted axes (z, x, y) become derivatives
+ * along (x, y, z)).
+ *   normalization  0 "integral": c_l = 1 (this library's, unit L2 norm on
+ *                  the sphere); 1 "component": c_l = sqrt(4 pi), so that
+ *                  sum_m Y_lm^2 = 2l+1 on the unit sphere; 2 "norm":
+ *                  c_l = sqrt(4 pi / (2l+1)), so that the sum is 1
+ *   Y              in/out [n,K] (required)
+ *   dY             in/out [n,3,K] (may be NULL)
+ * Errors: SPH_ERR_NULL for a NULL Y with n > 0; SPH_ERR_LMAX; SPH_ERR_INVALID
+ * for n < 0, a bad dtype or normalization, or overlapping Y and dY.
+ */
+int32_t sph_e3nn_convert(int64_t n, int32_t l_max, int32_t normalization,
+                         int32_t dtype, void* Y, void* dY, void* stream);
+
+/*
  * sph_batched_compute -- many neighbour lists in one persistent launch.
  * The points of n_env environments are concatenated (CSR): environment e
  * owns rows offsets[e] .. offsets[e+1]-1 of xyz (Sec. III: the harmonics of

@@ -38,6 +38,7 @@ from .derived import (  # noqa: F401
     hessian_contract,
     radial_expansion,
     radial_expansion_backward,
+    e3nn_convention,
     per_l_errors,
     component_scales,
 )

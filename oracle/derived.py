@@ -123,6 +123,40 @@ def radial_expansion_backward(xyz, offsets, R, G, l_max: int, normalize: bool):
     return gx, gR
 
 
+# ------------------------------------------------------ e3nn's conventions
+E3NN_NORMALIZATIONS = ("integral", "component", "norm")
+
+
+def e3nn_convention(xyz, l_max: int, normalize: bool, normalization: str = "integral"):
+    """``(Y [N,K], dY [N,3,K])`` in e3nn's conventions, longdouble.
+
+    Sec. III.B says the method's library provides wrappers following e3nn's
+    conventions without stating them; the reading here: y is the polar
+    axis, i.e. the harmonics of Eq. real-sh-cartesian evaluated at the
+    cyclically permuted point (z, x, y), so that degree 1 is proportional to
+    (x, y, z) in that order; "integral" keeps the unit L2 norm on the
+    sphere, "component" multiplies degree l by sqrt(4 pi) (sum over m of
+    Y^2 = 2l+1 on the unit sphere), "norm" by sqrt(4 pi / (2l+1)) (sum 1).
+    Derivatives are along the caller's x, y, z (chain rule through the
+    permutation).
+    """
+    if normalization not in E3NN_NORMALIZATIONS:
+        raise ValueError(normalization)
+    xyz = np.asarray(xyz)
+    perm = np.stack([xyz[:, 2], xyz[:, 0], xyz[:, 1]], axis=1)
+    Y, dYp = real_sph(perm, l_max, normalize, gradients=True)
+    # d/dx = d/dy', d/dy = d/dz', d/dz = d/dx'  for (x', y', z') = (z, x, y)
+    dY = np.stack([dYp[:, 1], dYp[:, 2], dYp[:, 0]], axis=1)
+    ls = np.array([l for l in range(l_max + 1) for _ in range(2 * l + 1)])
+    if normalization == "integral":
+        c = np.ones(ls.size, dtype=LD)
+    elif normalization == "component":
+        c = np.full(ls.size, np.sqrt(LD(4) * np.arccos(LD(-1))), dtype=LD)
+    else:
+        c = np.sqrt(LD(4) * np.arccos(LD(-1)) / (2 * ls + 1).astype(LD))
+    return Y * c, dY * c
+
+
 # ------------------------------------------------------------ error metric
 def _ls(l_max):
     return np.array([l for l in range(l_max + 1) for _ in range(2 * l + 1)], dtype=np.float64)

@@ -9,7 +9,8 @@ include/sph.h).  This package is its thin Python face:
   ...), torch tensors in,
   raw device pointers and the current HIP stream out;
 * :mod:`.autograd` -- ``spherical_harmonics`` / ``SphericalHarmonics`` with
-  first and second derivatives.
+  first and second derivatives, and ``e3nn_spherical_harmonics`` in e3nn's
+  conventions (first derivatives).
 
 Building: ``python -m paper_2302_08381_amd.build`` (hipcc, in-tree).
 """
@@ -27,12 +28,16 @@ from ._native import (  # noqa: F401
     sph_compute_with_gradients,
     sph_compute_with_hessians,
     sph_double_backward,
+    sph_e3nn_convert,
+    sph_e3nn_coordinates,
     sph_radial_expansion,
     sph_radial_expansion_backward,
     version,
 )
 from .autograd import (  # noqa: F401
     SphericalHarmonics,
+    e3nn_spherical_harmonics,
+    e3nn_spherical_harmonics_with_gradients,
     spherical_harmonics,
     spherical_harmonics_with_gradients,
 )

@@ -49,6 +49,8 @@ _SIGNATURES = {
     "sph_radial_expansion": (_i32, [_vp, _vp, _i64, _i64, _vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp]),
     "sph_radial_expansion_backward": (_i32, [_vp, _vp, _i64, _i64, _vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp,
                                               _vp, _vp]),
+    "sph_e3nn_coordinates": (_i32, [_vp, _i64, _i32, _vp, _vp]),
+    "sph_e3nn_convert": (_i32, [_i64, _i32, _i32, _i32, _vp, _vp, _vp]),
     "sph_batched_set_options": (_i32, [_i32, _i32]),
     "sph_batched_get_config": (_i32, [_i32, _i32, _i32, _i32, _i32, ctypes.c_char_p, _i32]),
     "sph_batched_set_config": (_i32, [_i32, _i32, _i32, _i32, _i32, _i32, _i32]),
@@ -198,6 +200,39 @@ def sph_compute_with_gradients(xyz: torch.Tensor, l_max: int, normalize: bool = 
     with torch.cuda.device(xyz.device):
         _check(lib().sph_compute_with_gradients(_ptr(xyz), n, int(l_max), int(bool(normalize)),
                                                 _dtype_code(xyz), _ptr(Y), _ptr(dY), _stream(xyz.device)))
+    return Y, dY
+
+
+E3NN_NORMALIZATIONS = {"integral": 0, "component": 1, "norm": 2}
+
+
+def sph_e3nn_coordinates(xyz: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """(z, x, y) of every point (include/sph.h: sph_e3nn_coordinates); ``out``
+    may be ``xyz`` itself."""
+    _check_xyz(xyz)
+    n = xyz.shape[0]
+    if out is None:
+        out = torch.empty_like(xyz)
+    else:
+        _need(out, "out", (n, 3), xyz.dtype, xyz.device)
+    with torch.cuda.device(xyz.device):
+        _check(lib().sph_e3nn_coordinates(_ptr(xyz), n, _dtype_code(xyz), _ptr(out), _stream(xyz.device)))
+    return out
+
+
+def sph_e3nn_convert(Y: torch.Tensor, dY: torch.Tensor | None, l_max: int, normalization: str = "integral"):
+    """In place: Y (and dY) computed at sph_e3nn_coordinates' points into
+    e3nn's convention (include/sph.h: sph_e3nn_convert).  Returns (Y, dY)."""
+    if normalization not in E3NN_NORMALIZATIONS:
+        raise ValueError(f"normalization must be one of {sorted(E3NN_NORMALIZATIONS)}")
+    n = Y.shape[0]
+    K = (int(l_max) + 1) ** 2 if l_max >= 0 else 0
+    _need(Y, "Y", (n, K), Y.dtype, Y.device)
+    if dY is not None:
+        _need(dY, "dY", (n, 3, K), Y.dtype, Y.device)
+    with torch.cuda.device(Y.device):
+        _check(lib().sph_e3nn_convert(n, int(l_max), E3NN_NORMALIZATIONS[normalization], _dtype_code(Y), _ptr(Y),
+                                      _ptr(dY), _stream(Y.device)))
     return Y, dY
 
 

@@ -71,6 +71,43 @@ def spherical_harmonics_with_gradients(xyz: torch.Tensor, l_max: int, normalize:
         return _native.sph_compute_with_gradients(xyz.contiguous(), l_max, normalize)
 
 
+class _SphE3nn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, xyz, l_max, normalize, normalization):
+        ctx.l_max = l_max
+        xp = _native.sph_e3nn_coordinates(xyz)
+        Y, dY = _native.sph_compute_with_gradients(xp, l_max, normalize)
+        _native.sph_e3nn_convert(Y, dY, l_max, normalization)
+        ctx.save_for_backward(dY)
+        return Y
+
+    @staticmethod
+    def backward(ctx, grad_Y):
+        (dY,) = ctx.saved_tensors
+        return _native.sph_backward(dY, grad_Y.contiguous(), ctx.l_max), None, None, None
+
+
+def e3nn_spherical_harmonics(xyz: torch.Tensor, l_max: int, normalize: bool = True,
+                             normalization: str = "integral") -> torch.Tensor:
+    """Y[n,(l_max+1)^2] in e3nn's convention (Sec. III.B): degrees 0..l_max,
+    y as the polar axis, ``normalization`` "integral", "component" or
+    "norm"; differentiable once w.r.t. xyz.  Permutation, forward and
+    conversion all run in the library's kernels (include/sph.h:
+    sph_e3nn_coordinates, sph_e3nn_convert)."""
+    if normalization not in _native.E3NN_NORMALIZATIONS:
+        raise ValueError(f"normalization must be one of {sorted(_native.E3NN_NORMALIZATIONS)}")
+    return _SphE3nn.apply(xyz.contiguous(), int(l_max), bool(normalize), normalization)
+
+
+def e3nn_spherical_harmonics_with_gradients(xyz: torch.Tensor, l_max: int, normalize: bool = True,
+                                            normalization: str = "integral"):
+    """(Y, dY) in e3nn's convention without autograd; dY[n,3,K] along x, y, z."""
+    with torch.no_grad():
+        xp = _native.sph_e3nn_coordinates(xyz.contiguous())
+        Y, dY = _native.sph_compute_with_gradients(xp, l_max, normalize)
+        return _native.sph_e3nn_convert(Y, dY, l_max, normalization)
+
+
 class SphericalHarmonics(torch.nn.Module):
     """Module form: ``SphericalHarmonics(l_max, normalize)(xyz) -> Y``."""
 

@@ -46,6 +46,7 @@ SOURCES = [
     "sph_kernels_expand_f64.hip",
     "sph_kernels_hess_f32.hip",
     "sph_kernels_hess_f64.hip",
+    "sph_kernels_e3nn.hip",
     "sph_api.cpp",
 ]
 COMMON = [

@@ -450,6 +450,41 @@ int32_t sph_compute_with_hessians(const void* xyz, int64_t n, int32_t l_max, int
   return ok();
 }
 
+int32_t sph_e3nn_coordinates(const void* xyz, int64_t n, int32_t dtype, void* xyz_p, void* stream) {
+  if (n < 0) return fail(SPH_ERR_INVALID, "n must be >= 0");
+  if (dtype != SPH_F32 && dtype != SPH_F64) return fail(SPH_ERR_INVALID, "dtype must be SPH_F32 or SPH_F64");
+  if (n == 0) return ok();
+  if (xyz == nullptr || xyz_p == nullptr) return fail(SPH_ERR_NULL, "xyz and xyz_p are required");
+  const size_t bytes = static_cast<size_t>(n) * 3 * elem_size(dtype);
+  int32_t st;
+  if (xyz_p != xyz &&
+      (st = check_no_overlap({{xyz_p, bytes, "xyz_p"}}, {{xyz, bytes, "xyz"}, {xyz_p, bytes, "xyz_p"}})) != SPH_OK)
+    return st;
+  const hipError_t e = sph::e3nn_coordinates_launch(dtype == SPH_F64, xyz, n, xyz_p, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_fail(e, "e3nn coordinates launch");
+  return ok();
+}
+
+int32_t sph_e3nn_convert(int64_t n, int32_t l_max, int32_t normalization, int32_t dtype, void* Y, void* dY,
+                         void* stream) {
+  int32_t st = check_common(n, l_max, dtype);
+  if (st != SPH_OK) return st;
+  if (normalization < 0 || normalization > 2)
+    return fail(SPH_ERR_INVALID, "normalization must be 0 (integral), 1 (component) or 2 (norm)");
+  if (n == 0) return ok();
+  if (Y == nullptr) return fail(SPH_ERR_NULL, "Y is required");
+  const size_t w = elem_size(dtype);
+  const size_t K = static_cast<size_t>(sph_num_components(l_max));
+  const size_t un = static_cast<size_t>(n);
+  if ((st = check_no_overlap({{Y, un * K * w, "Y"}, {dY, un * 3 * K * w, "dY"}},
+                             {{Y, un * K * w, "Y"}, {dY, un * 3 * K * w, "dY"}})) != SPH_OK)
+    return st;
+  const hipError_t e =
+      sph::e3nn_convert_launch(dtype == SPH_F64, n, l_max, normalization, Y, dY, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_fail(e, "e3nn convert launch");
+  return ok();
+}
+
 int32_t sph_radial_expansion(const void* xyz, const int64_t* offsets, int64_t n_env, int64_t n_points,
                              const void* R, int32_t n_max, int32_t l_max, int32_t normalize, int32_t dtype,
                              void* c, int32_t* status, void* stream) {

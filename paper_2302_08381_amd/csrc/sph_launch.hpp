@@ -200,5 +200,10 @@ KernelInfo expand_info_f64(int L, int normalize, int n_max);
 // do not fit one block's LDS).
 KernelInfo expand_bwd_info_f32(int L, int normalize, int n_max);
 KernelInfo expand_bwd_info_f64(int L, int normalize, int n_max);
+// e3nn's conventions: the permuted coordinates and the in-place conversion
+// of Y and dY (dtype64: double, else float).
+hipError_t e3nn_coordinates_launch(int dtype64, const void* xyz, int64_t n, void* out, hipStream_t s);
+hipError_t e3nn_convert_launch(int dtype64, int64_t n, int L, int normalization, void* Y, void* dY,
+                               hipStream_t s);
 
 }  // namespace sph

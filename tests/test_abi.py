@@ -177,3 +177,18 @@ def test_radial_expansion_backward_validation(lib):
     assert x(FAKE, FAKE, 3, 10, FAKE, 8, 4, 1, 0, None, FAKE, None, None, None) == 1    # grad_c NULL
     assert x(FAKE, FAKE, 3, 10, FAKE, 8, 40, 1, 0, FAKE, FAKE, None, None, None) == 3   # l_max
     assert x(FAKE, FAKE, 3, 10, FAKE, 8, 4, 1, 0, FAKE, None, None, None, None) == 0    # nothing requested
+
+
+def test_e3nn_entry_points_validation(lib):
+    """Every case fails validation before any device call."""
+    assert lib.sph_e3nn_coordinates(FAKE, -1, 0, FAKE, None) == 2          # n < 0
+    assert lib.sph_e3nn_coordinates(FAKE, 5, 3, FAKE, None) == 2           # dtype
+    assert lib.sph_e3nn_coordinates(None, 5, 0, FAKE, None) == 1           # NULL input
+    assert lib.sph_e3nn_coordinates(None, 0, 0, None, None) == 0           # nothing to do
+    base = 0x100000
+    assert lib.sph_e3nn_coordinates(ctypes.c_void_p(base), 10, 0, ctypes.c_void_p(base + 8), None) == 2  # overlap
+    assert lib.sph_e3nn_convert(5, 4, 3, 0, FAKE, None, None) == 2         # normalization
+    assert lib.sph_e3nn_convert(5, 33, 0, 0, FAKE, None, None) == 3        # l_max
+    assert lib.sph_e3nn_convert(5, 4, 0, 0, None, None, None) == 1         # Y required
+    assert lib.sph_e3nn_convert(10, 2, 1, 0, ctypes.c_void_p(base), ctypes.c_void_p(base + 64), None) == 2
+    assert lib.sph_e3nn_convert(0, 2, 1, 0, None, None, None) == 0

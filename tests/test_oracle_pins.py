@@ -518,3 +518,76 @@ def test_radial_expansion_backward_by_differences(normalize):
     lhs = float((gR * dR).sum())
     rhs = float((oracle.radial_expansion(pts, offs, dR, L, normalize) * G).sum())
     assert abs(lhs - rhs) <= 1e-13 * (1 + abs(rhs))
+
+
+# ------------------------------------------------------ e3nn's conventions
+# The reading of Sec. III.B (e3nn's conventions, not stated in the paper):
+# y as the polar axis, degree 1 proportional to (x, y, z) in that order,
+# normalisations "integral" / "component" / "norm".  e3nn is not installed,
+# so beyond these properties the ordering within a degree is parity
+# unpinned.
+@pytest.mark.parametrize("normalize", [True, False])
+def test_e3nn_degree_one_is_the_point(normalize):
+    """Component normalisation: Y_0 = 1 and Y_1 = sqrt(3) (x, y, z) / r (times r
+    for the scaled harmonics)."""
+    p = _pts(50, 801)
+    Y, _ = oracle.e3nn_convention(p, 1, normalize, "component")
+    r = np.linalg.norm(p, axis=1, keepdims=True)
+    want1 = math.sqrt(3) * (p / r if normalize else p)
+    assert np.allclose(np.asarray(Y[:, 0], float), 1.0, rtol=1e-15, atol=0)
+    assert np.abs(np.asarray(Y[:, 1:4], float) - want1).max() <= 1e-14 * max(1.0, float(np.abs(want1).max()))
+    # the other cyclic order, (y, z, x), does not give it
+    Yalt, _ = oracle.real_sph(p[:, [1, 2, 0]], 1, normalize)
+    assert np.abs(math.sqrt(4 * PI) * np.asarray(Yalt[:, 1:4], float) - want1).max() > 0.1
+
+
+@pytest.mark.parametrize("normalization,target", [("integral", lambda l: (2 * l + 1) / (4 * PI)),
+                                                  ("component", lambda l: 2 * l + 1),
+                                                  ("norm", lambda l: 1.0)])
+def test_e3nn_normalisation_sums(normalization, target):
+    """Addition theorem: sum_m Y_lm(u)^2 on the unit sphere is (2l+1)/(4 pi)
+    for unit L2 norm, times the square of the per-degree factor."""
+    p = _pts(40, 802)
+    u = p / np.linalg.norm(p, axis=1, keepdims=True)
+    L = 8
+    Y, _ = oracle.e3nn_convention(u, L, False, normalization)
+    Y = np.asarray(Y, float)
+    for l in range(L + 1):
+        s = (Y[:, l * l:(l + 1) ** 2] ** 2).sum(1)
+        assert np.allclose(s, target(l), rtol=1e-13, atol=0), (normalization, l)
+
+
+def test_e3nn_polar_axis_is_y():
+    """On the y axis only the m = 0 column of each degree survives, with
+    Y_l0(0, +-1, 0) = (+-1)^l sqrt((2l+1) / (4 pi)) (Legendre P_l(+-1)) for
+    unit L2 norm; elsewhere on the sphere the m != 0 columns do not vanish."""
+    L = 10
+    p = np.array([[0.0, 1.0, 0.0], [0.0, -1.0, 0.0]])
+    Y, _ = oracle.e3nn_convention(p, L, True, "integral")
+    Y = np.asarray(Y, float)
+    for l in range(L + 1):
+        row = Y[:, l * l:(l + 1) ** 2].copy()
+        want = math.sqrt((2 * l + 1) / (4 * PI))
+        assert abs(row[0, l] - want) < 1e-14 and abs(row[1, l] - (-1) ** l * want) < 1e-14
+        row[:, l] = 0
+        assert np.abs(row).max() < 1e-14, l
+    Yz, _ = oracle.e3nn_convention(np.array([[0.0, 0.0, 1.0]]), L, True, "integral")
+    assert np.abs(np.asarray(Yz, float)[0, 4:9]).max() > 0.1  # the z axis is not the pole
+
+
+@pytest.mark.parametrize("normalize", [True, False])
+@pytest.mark.parametrize("normalization", ["integral", "component", "norm"])
+def test_e3nn_gradient_by_differences(normalize, normalization):
+    """dY[:, a] is the derivative along the caller's axis a (central
+    differences of Y, h = 1e-6 in longdouble)."""
+    p = _pts(20, 803)
+    L = 6
+    _, dY = oracle.e3nn_convention(p, L, normalize, normalization)
+    h = 1e-6
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = h
+        Yp, _ = oracle.e3nn_convention(p + e, L, normalize, normalization)
+        Ym, _ = oracle.e3nn_convention(p - e, L, normalize, normalization)
+        fd = np.asarray((Yp - Ym) / (2 * h), float)
+        assert np.abs(np.asarray(dY[:, a], float) - fd).max() < 1e-7 * max(1.0, float(np.abs(fd).max())), a
