@@ -376,7 +376,19 @@ def extras(dev):
     tv = _time(lambda: sph.sph_compute(x32, L_MAX, NORMALIZE, Y=Yv), 30)
     out["values_only_l8_f32"] = {"s": tv, "points_per_s": N_POINTS / tv,
                                  "GB_per_s": N_POINTS * 4 * (3 + K) / tv / 1e9}
-    del x32, Yv
+    # e3nn's conventions, Y+dY: permuted points, the forward, the in-place conversion
+    xp = torch.empty_like(x32)
+    Ye = torch.empty((N_POINTS, K), dtype=torch.float32, device=dev)
+    dYe = torch.empty((N_POINTS, 3, K), dtype=torch.float32, device=dev)
+
+    def e3nn_call():
+        sph.sph_e3nn_coordinates(x32, out=xp)
+        sph.sph_compute_with_gradients(xp, L_MAX, NORMALIZE, Y=Ye, dY=dYe)
+        sph.sph_e3nn_convert(Ye, dYe, L_MAX, "component")
+    te = _time(e3nn_call, 20)
+    out["e3nn_component_l8_f32"] = {"s": te, "points_per_s": N_POINTS / te,
+                                    "note": "Y+dY in e3nn's conventions; the conversion re-reads and rewrites Y, dY"}
+    del x32, Yv, xp, Ye, dYe
     # double backward: 4e6 points in the ball 0.5..5, l_max = 6, float32, normalised
     n3, L3 = 4_000_000, 6
     K3 = (L3 + 1) ** 2

@@ -18,8 +18,11 @@ exactly, up to rounding; Sec. II):
   route (Eq. recur-p, Condon-Shortley phase) in numpy ``longdouble``, with the
   gradient from textbook pole-free Ferrers identities.  Stable at any l <= 32.
 * :mod:`oracle.derived` -- backward and double-backward contractions, the
-  radial expansion over environments (Eq. expansion) and the per-l error
-  metric, built on the two tiers.
+  radial expansion over environments (Eq. expansion), e3nn's conventions
+  (Sec. III.B, a reading: pinned by the degree-1 identity, normalisation
+  sums, the polar axis and finite differences; beyond those pins parity
+  unpinned, e3nn not being installed) and the per-l error metric, built on
+  the two tiers.
 
 Pins (tests marked ``not gpu``) tie both tiers to closed forms, library
 routines (mpmath), invariants (addition theorems, orthonormality, harmonicity,
