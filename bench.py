@@ -539,6 +539,9 @@ SUITE_COMMANDS = {
     "tcc": "rocprofv3 --pmc TCC_EA0_WRREQ_sum TCC_EA0_WRREQ_64B_sum TCC_EA0_WRREQ_LEVEL_sum GRBM_GUI_ACTIVE "
            "--output-format csv -d {out}/suite_tcc -o run -- "
            "python3 {repo}/bench.py --profile-suite --steps 2 --warmup 1",
+    "wait": "rocprofv3 --pmc SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_LDS_IDX_ACTIVE SQ_WAVE_CYCLES GRBM_GUI_ACTIVE "
+            "--output-format csv -d {out}/suite_wait -o run -- "
+            "python3 {repo}/bench.py --profile-suite --steps 2 --warmup 1",
 }
 SUITE_STEPS = 5  # the --steps of the trace command
 
@@ -610,6 +613,8 @@ def summarize_suite(outdir: str) -> None:
     sq = _per_dispatch(os.path.join(outdir, "suite_sq", "run_counter_collection.csv"))
     tcc_path = os.path.join(outdir, "suite_tcc", "run_counter_collection.csv")
     tcc = _per_dispatch(tcc_path) if os.path.exists(tcc_path) else {}
+    wait_path = os.path.join(outdir, "suite_wait", "run_counter_collection.csv")
+    wait = _per_dispatch(wait_path) if os.path.exists(wait_path) else {}
 
     def mean_counter(tbl, tag, name):
         v = [c[name] for k, c, _ in tbl.values() if tag in k and name in c]
@@ -619,10 +624,11 @@ def summarize_suite(outdir: str) -> None:
     ws = REFERENCE_COPY_BYTES / (mean_counter(write, REFERENCE_COPY, "WRITE_SIZE") * 1024)
     lines = ["# Kernel suite: time, bytes and SQ counters of every kernel of the path", "",
              "Commands (from /tmp, TMPDIR=/tmp), each in a run of its own:", ""]
-    lines += ["    " + cmds[k] for k in ("trace", "fetch", "write", "sq") + (("tcc",) if tcc else ())]
+    lines += ["    " + cmds[k] for k in ("trace", "fetch", "write", "sq") + (("tcc",) if tcc else ())
+              + (("wait",) if wait else ())]
     # the hash the profiled runs printed (the sources they ran), not the tree's
     run_hashes = set()
-    for k in ("trace", "fetch", "write", "sq", "tcc"):
+    for k in ("trace", "fetch", "write", "sq", "tcc", "wait"):
         log = os.path.join(outdir, f"suite_{k}.log")
         if os.path.exists(log):
             with open(log) as f:
@@ -688,6 +694,22 @@ def summarize_suite(outdir: str) -> None:
             wk = mean_counter(write, tag, "WRITE_SIZE")
             wgbs = f"{wk * ws * 1024 / mean / 1e9:.0f}" if wk is not None else ""
             lines.append(f"| {role} | {mean * 1e6:.1f} | {req:.4g} | {r64 / req:.3f} | {lvl / cyc:.0f} | {wgbs} |")
+    if wait:
+        # where the waves' time goes: waiting on results of memory, LDS or
+        # scalar loads (s_waitcnt), waiting to issue, and how busy the LDS is
+        lines += ["", "Wave time (SQ_WAIT_ANY: wave quad-cycles waiting on outstanding memory, LDS or scalar "
+                  "results; SQ_WAIT_INST_ANY: waiting to issue; both over SQ_WAVE_CYCLES) and LDS busy "
+                  "(SQ_LDS_IDX_ACTIVE cycles per CU-cycle):", "",
+                  "| kernel | waiting on results | waiting to issue | LDS busy |", "|---|---|---|---|"]
+        for role, tag, _, _ in _suite_workloads():
+            w = {n: mean_counter(wait, tag, n) for n in ("SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_LDS_IDX_ACTIVE",
+                                                        "SQ_WAVE_CYCLES", "GRBM_GUI_ACTIVE")}
+            if any(v is None for v in w.values()):
+                continue
+            cyc = w["GRBM_GUI_ACTIVE"] / XCD_NUM
+            lines.append(f"| {role} | {100 * w['SQ_WAIT_ANY'] / w['SQ_WAVE_CYCLES']:.0f} % | "
+                         f"{100 * w['SQ_WAIT_INST_ANY'] / w['SQ_WAVE_CYCLES']:.0f} % | "
+                         f"{100 * w['SQ_LDS_IDX_ACTIVE'] / (CU_NUM * cyc):.0f} % |")
     with open(os.path.join(ROOT, "profiles", "kernel_suite.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
