@@ -90,11 +90,12 @@ __device__ __forceinline__ void dbwd_group(const Point<T>& pt, T vx, T vy, T vz,
     q_row_rt<T, MM>(l, ez, pt.rxy2, cur);
     const int k0 = l * l + l;
     T Sgv = T(0), Sgx = T(0), Sgy = T(0), Sgz = T(0), Sy = T(0);
+    const T luv = T(l) * uv;  // normalised: grad Y . v = (grad Yt . v - l (u.v) Yt) / r
     auto process = [&](int k, T Yt, T gx, T gy, T gz, T gv, T hx, T hy, T hz) {
       const T w = row[k];
       if (write_gg) {
         T gg = gv;
-        if constexpr (NORM) gg = (gv - T(l) * Yt * uv) * pt.inv_r;
+        if constexpr (NORM) gg = (gv - luv * Yt) * pt.inv_r;
         row[k] = gg;
       }
       A.hx += w * hx;
@@ -140,30 +141,40 @@ __device__ __forceinline__ void dbwd_group(const Point<T>& pt, T vx, T vy, T vz,
         process(k0, q * kIS2, Qx * kIS2, Qy * kIS2, Cz * kIS2, gQv * kIS2, Hx * kIS2,
                 Hy * kIS2, Hz * kIS2);
       } else if constexpr (kTab) {
+        // The columns k0 + m (t = c_m, grad t = (mc, -ms), H(t) v = (hA, -hB))
+        // and k0 - m (t = s_m, grad t = (ms, mc), H(t) v = (hB, hA)) of one
+        // order, taken together: everything accumulated is linear in their
+        // weights wp, wm, so the pair folds into P = wp c + wm s and five
+        // like combinations before it meets the row's Hessian terms.
         const int mt = kTab ? m : 0;
         const T c = tc[mt], sm = ts[mt], mc = tmc[mt], ms = tms[mt];
-        const T hA = thA[mt], hB = thB[mt];
-        {  // +m: t = c_m, grad t = (mc, -ms), H(t) v = (hA, -hB)
-          const T tv = tvc[mt];
-          const T gx = c * Qx + q * mc;
-          const T gy = c * Qy - q * ms;
-          const T gz = c * Cz;
-          const T gv = c * gQv + q * tv;
-          const T hx = c * Hx + Qx * tv + mc * gQv + q * hA;
-          const T hy = c * Hy + Qy * tv - ms * gQv - q * hB;
-          const T hz = c * Hz + Cz * tv;
-          process(k0 + m, q * c, gx, gy, gz, gv, hx, hy, hz);
+        const T hA = thA[mt], hB = thB[mt], tvp = tvc[mt], tvm = tvs[mt];
+        const int kp = k0 + m, km = k0 - m;
+        const T wp = row[kp], wm = row[km];
+        if (write_gg) {  // grad Y . v of each column
+          T ggp = c * gQv + q * tvp, ggm = sm * gQv + q * tvm;
+          if constexpr (NORM) {
+            ggp = (ggp - luv * (q * c)) * pt.inv_r;
+            ggm = (ggm - luv * (q * sm)) * pt.inv_r;
+          }
+          row[kp] = ggp;
+          row[km] = ggm;
         }
-        {  // -m: t = s_m, grad t = (ms, mc), H(t) v = (hB, hA)
-          const T tv = tvs[mt];
-          const T gx = sm * Qx + q * ms;
-          const T gy = sm * Qy + q * mc;
-          const T gz = sm * Cz;
-          const T gv = sm * gQv + q * tv;
-          const T hx = sm * Hx + Qx * tv + ms * gQv + q * hB;
-          const T hy = sm * Hy + Qy * tv + mc * gQv + q * hA;
-          const T hz = sm * Hz + Cz * tv;
-          process(k0 - m, q * sm, gx, gy, gz, gv, hx, hy, hz);
+        const T P = wp * c + wm * sm;
+        const T Pt = wp * tvp + wm * tvm;
+        const T Pm = wp * mc + wm * ms;
+        const T Pn = wm * mc - wp * ms;
+        const T Ph = wp * hA + wm * hB;
+        const T Pk = wm * hA - wp * hB;
+        A.hx += Hx * P + Qx * Pt + gQv * Pm + q * Ph;
+        A.hy += Hy * P + Qy * Pt + gQv * Pn + q * Pk;
+        A.hz += Hz * P + Cz * Pt;
+        if constexpr (NORM) {
+          Sgx += Qx * P + q * Pm;
+          Sgy += Qy * P + q * Pn;
+          Sgz += Cz * P;
+          Sgv += gQv * P + q * Pt;
+          Sy += q * P;
         }
       } else {
         const T fm = T(m);
