@@ -395,7 +395,9 @@ def extras(dev):
     xb = torch.as_tensor(shell_points(n3, 0.5, 5.0, SEEDS["diff"]), dtype=torch.float32).to(dev)
     gYb = torch.as_tensor(standard_normal((n3, K3), 31), dtype=torch.float32).to(dev)
     vb = torch.as_tensor(standard_normal((n3, 3), 32), dtype=torch.float32).to(dev)
-    td = _time(lambda: sph.sph_double_backward(xb, gYb, vb, L3, True), 10)
+    ggb = torch.empty((n3, K3), dtype=torch.float32, device=dev)
+    g2b = torch.empty((n3, 3), dtype=torch.float32, device=dev)
+    td = _time(lambda: sph.sph_double_backward(xb, gYb, vb, L3, True, grad_grad_Y=ggb, grad_xyz2=g2b), 10)
     out["double_backward_l6_f32_4M"] = {"s": td, "points_per_s": n3 / td,
                                         "GB_per_s": n3 * 4 * (3 + K3 + 3 + K3 + 3) / td / 1e9}
     # ... and its first backward, from the forward's stored dY
@@ -413,7 +415,7 @@ def extras(dev):
     out["hessians_l6_f32_4M"] = {"s": th, "points_per_s": n3 / th,
                                  "GB_per_s": n3 * 4 * (3 + 13 * K3) / th / 1e9,
                                  "bytes": "read xyz, write Y, dY and d2Y: N*4*(3 + 13K)"}
-    del xb, gYb, vb, Y3, dY3, gx3, d2Y3
+    del xb, gYb, vb, Y3, dY3, gx3, d2Y3, ggb, g2b
     # plain method, CPU-sized: N = 1000, float64, l_max = 4 (launch-bound)
     x1 = torch.as_tensor(standard_normal_points(1000, SEEDS["plain_cpu"]), dtype=torch.float64).to(dev)
     t1 = _time(lambda: sph.sph_compute_with_gradients(x1, 4, True), 50)

@@ -281,15 +281,22 @@ def sph_backward(dY: torch.Tensor, grad_Y: torch.Tensor, l_max: int, grad_xyz: t
 
 
 def sph_double_backward(xyz: torch.Tensor, grad_Y: torch.Tensor, v: torch.Tensor, l_max: int,
-                        normalize: bool = True, want_grad_grad_Y: bool = True, want_grad_xyz: bool = True):
-    """(grad_grad_Y[n,K] or None, grad_xyz2[n,3] or None) (include/sph.h: sph_double_backward)."""
+                        normalize: bool = True, want_grad_grad_Y: bool = True, want_grad_xyz: bool = True,
+                        grad_grad_Y: torch.Tensor | None = None, grad_xyz2: torch.Tensor | None = None):
+    """(grad_grad_Y[n,K] or None, grad_xyz2[n,3] or None) (include/sph.h: sph_double_backward);
+    the outputs may be preallocated."""
     _check_xyz(xyz)
     n = xyz.shape[0]
     K = (int(l_max) + 1) ** 2
     _need(grad_Y, "grad_Y", (n, K), xyz.dtype, xyz.device)
     _need(v, "v", (n, 3), xyz.dtype, xyz.device)
-    ggY = torch.empty((n, K), dtype=xyz.dtype, device=xyz.device) if want_grad_grad_Y else None
-    g2 = torch.empty((n, 3), dtype=xyz.dtype, device=xyz.device) if want_grad_xyz else None
+    ggY = g2 = None
+    if want_grad_grad_Y:
+        ggY = torch.empty((n, K), dtype=xyz.dtype, device=xyz.device) if grad_grad_Y is None else \
+            _need(grad_grad_Y, "grad_grad_Y", (n, K), xyz.dtype, xyz.device)
+    if want_grad_xyz:
+        g2 = torch.empty((n, 3), dtype=xyz.dtype, device=xyz.device) if grad_xyz2 is None else \
+            _need(grad_xyz2, "grad_xyz2", (n, 3), xyz.dtype, xyz.device)
     with torch.cuda.device(xyz.device):
         _check(lib().sph_double_backward(_ptr(xyz), _ptr(grad_Y), _ptr(v), n, int(l_max),
                                          int(bool(normalize)), _dtype_code(xyz), _ptr(ggY), _ptr(g2),
