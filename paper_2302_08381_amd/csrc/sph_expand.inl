@@ -184,7 +184,33 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandParams P) {
     return scan();
   };
   T px = T(0), py = T(0), pz = T(0);
-  T rb[RB];
+  // The radial batch: RB values per thread, as RB / W 16-byte vectors when
+  // the channels need no padding and R is 16-byte aligned (every row is then
+  // a whole number of vectors, the tile a copy of the global block), else
+  // element by element into the padded rows.
+  using RV = typename Vec16<T>::type;
+  constexpr int RW = Vec16<T>::n;
+  static_assert(RB % RW == 0, "whole radial vectors");
+  constexpr int RBV = RB / RW;
+  const bool rvec = NP == NM && aligned16(R);
+  RV rb[RBV];
+  auto rload = [&](const T* Rg, int base, int nrv) {  // values base .. base + RB * 128 of the chunk
+    if (rvec) {
+      const RV* g = reinterpret_cast<const RV*>(Rg);
+      const int nv = nrv / RW;
+#pragma unroll
+      for (int u = 0; u < RBV; ++u) {
+        const int i = base / RW + tid + u * kExpandThreads;
+        rb[u] = g[i < nv ? i : nv - 1];
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        const int i = base + tid + u * kExpandThreads;
+        rb[u / RW][u % RW] = Rg[i < nrv ? i : nrv - 1];
+      }
+    }
+  };
   auto issue = [&]() {  // coordinates and first radial batch of chunk (e, j0)
     int cnt = 0, cut = 0;
     bool span = false;
@@ -194,21 +220,25 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandParams P) {
     px = xyz[jp * 3 + 0];
     py = xyz[jp * 3 + 1];
     pz = xyz[jp * 3 + 2];
-    const int nrv = cnt * (L + 1) * NM;
-    const T* Rg = R + j0 * (L + 1) * NM;
-#pragma unroll
-    for (int u = 0; u < RB; ++u) {
-      const int i = tid + u * kExpandThreads;
-      rb[u] = Rg[i < nrv ? i : nrv - 1];
-    }
+    rload(R + j0 * (L + 1) * NM, 0, cnt * (L + 1) * NM);
   };
   auto rstore = [&](int base, int nrv) {
+    if (rvec) {
+      RV* sv = reinterpret_cast<RV*>(sR);
+      const int nv = nrv / RW;
 #pragma unroll
-    for (int u = 0; u < RB; ++u) {
-      const int i = base + tid + u * kExpandThreads;
-      if (i < nrv) {
-        const int row = NP == NM ? 0 : i / NM;
-        sR[NP == NM ? i : row * NP + (i - row * NM)] = rb[u];
+      for (int u = 0; u < RBV; ++u) {
+        const int i = base / RW + tid + u * kExpandThreads;
+        if (i < nv) sv[i] = rb[u];
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        const int i = base + tid + u * kExpandThreads;
+        if (i < nrv) {
+          const int row = NP == NM ? 0 : i / NM;
+          sR[NP == NM ? i : row * NP + (i - row * NM)] = rb[u / RW][u % RW];
+        }
       }
     }
   };
@@ -230,12 +260,7 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandParams P) {
     const T x = px, y = py, z = pz;
     // radial values past the first batch (chunks of more than RB * 128)
     for (int base = RB * kExpandThreads; base < nrv; base += RB * kExpandThreads) {
-      const T* Rg = R + c0 * (L + 1) * NM;
-#pragma unroll
-      for (int u = 0; u < RB; ++u) {
-        const int i = base + tid + u * kExpandThreads;
-        rb[u] = Rg[i < nrv ? i : nrv - 1];
-      }
+      rload(R + c0 * (L + 1) * NM, base, nrv);
       __builtin_amdgcn_s_waitcnt(kWaitVmem0);
       rstore(base, nrv);
     }
