@@ -777,13 +777,26 @@ __global__ __launch_bounds__(kWave) void k_expand_bwd(ExpandBwdParams P) {
   j0 = b;
   int se = 0;                         // the slice of environment e
   int64_t in_cur = -1, in_oth = -1;  // environments whose G slices se, 1 - se hold
+  // G of one environment into a slice, [n][k] -> [k][n] (padding channels
+  // zero): per column k of the lane, all NPC channels are loaded before any
+  // is stored, so their latencies overlap (one wait per column, no division)
   auto load_slice = [&](int sl, int64_t env) {
     const T* ge = gc + env * NM * K;
     T* dst = sG + sl * slice;
-    for (int i = gl; i < NPC * K; i += GS) {
-      const int n = i / K;
-      const int k = i - n * K;
-      dst[k * NPC + n] = n < NM ? ge[i] : T(0);
+    for (int k = gl; k < K; k += GS) {
+      T v[NPC];
+#pragma unroll
+      for (int n = 0; n < NPC; ++n) v[n] = n < NM ? ge[n * K + k] : T(0);
+      using V = typename Vec16<T>::type;
+      constexpr int W = Vec16<T>::n;
+      V* d = reinterpret_cast<V*>(dst + k * NPC);
+#pragma unroll
+      for (int h = 0; h < NPC / W; ++h) {
+        V w;
+#pragma unroll
+        for (int u = 0; u < W; ++u) w[u] = v[h * W + u];
+        d[h] = w;
+      }
     }
   };
   while (__any(e < e_end)) {
