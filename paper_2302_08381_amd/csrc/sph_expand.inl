@@ -440,7 +440,9 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandParams P) {
 //            lane reads its 16-byte pieces of a row over several degrees,
 //            and with the nontemporal hint the lines left L2 between them
 //            and were fetched again (20-30 % slower);
-//   SRC = 2: global memory element by element.
+//   SRC = 2: global memory element by element (loading a degree ahead, as
+//            for SRC = 1, was 1-4 % slower: the second buffer costs
+//            occupancy).
 template <typename T, int MM, bool NORM, int NPC, int SRC>
 __device__ __forceinline__ void expand_bwd_point(const T* __restrict__ xyz, const T* __restrict__ R,
                                                  const T* __restrict__ sG, T* __restrict__ sRow,
@@ -630,8 +632,8 @@ __device__ __forceinline__ void expand_bwd_point(const T* __restrict__ xyz, cons
 // Copies of one group's radial tile between global rows [cnt][L+1][NM]
 // (contiguous from src) and LDS rows of stride RS, [L+1][NPC] each (NPC >= NM,
 // the padding channels zero).  VEC (NM == NPC, 16-byte aligned global rows):
-// 16-byte vectors, a batch of them in flight per lane; else element by
-// element.  GS lanes of the group take part (lane gl).
+// 16-byte vectors, a batch of them in flight per lane; else single elements,
+// also a batch in flight.  GS lanes of the group take part (lane gl).
 template <typename T, int NPC, int GS, bool VEC>
 __device__ __forceinline__ void expand_tile_in(T* __restrict__ sR, int RS, const T* __restrict__ src, int cnt,
                                                int L, int NM, int gl) {
@@ -663,11 +665,33 @@ __device__ __forceinline__ void expand_tile_in(T* __restrict__ sR, int RS, const
         if (i0 + u * GS < nv) *reinterpret_cast<V*>(sR + o[u]) = v[u];
     }
   } else {
-    const int row = (L + 1) * NPC;
-    for (int s = gl; s < cnt * row; s += GS) {
-      const int p = s / row, c = s - p * row;
-      const int l = c / NPC, n = c - l * NPC;
-      sR[p * RS + c] = n < NM ? src[(p * (L + 1) + l) * NM + n] : T(0);
+    // lane gl keeps channel n = gl % NPC and walks the rows r = p (L+1) + l
+    // of the tile, GS / NPC rows per step, NB loads in flight; the padding
+    // channels get zeros
+    static_assert(GS % NPC == 0, "whole rows per step");
+    constexpr int RPS = GS / NPC;
+    constexpr int NB = 8;
+    const int n = gl % NPC, L1 = L + 1, rows = cnt * L1;
+    int p = (gl / NPC) / L1, l = gl / NPC - p * L1;
+    const int qs = RPS / L1, rq = RPS - qs * L1;
+    for (int r0 = gl / NPC; r0 < rows; r0 += RPS * NB) {
+      T v[NB];
+      int o[NB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int r = r0 + u * RPS;
+        o[u] = p * RS + l * NPC + n;
+        v[u] = r < rows && n < NM ? src[r * NM + n] : T(0);
+        p += qs;
+        l += rq;
+        if (l >= L1) {
+          l -= L1;
+          ++p;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < NB; ++u)
+        if (r0 + u * RPS < rows) sR[o[u]] = v[u];
     }
   }
 }
@@ -693,11 +717,21 @@ __device__ __forceinline__ void expand_tile_out(const T* __restrict__ sR, int RS
       }
     }
   } else {
-    const int row = (L + 1) * NM;
-    for (int s = gl; s < cnt * row; s += GS) {
-      const int p = s / row, c = s - p * row;
-      const int l = c / NM, n = c - l * NM;
-      dst[s] = sR[p * RS + l * NPC + n];
+    // the walk of expand_tile_in: channel n = gl % NPC, GS / NPC rows a step
+    constexpr int RPS = GS / NPC;
+    const int n = gl % NPC, L1 = L + 1, rows = cnt * L1;
+    int p = (gl / NPC) / L1, l = gl / NPC - p * L1;
+    const int qs = RPS / L1, rq = RPS - qs * L1;
+    if (n < NM) {
+      for (int r = gl / NPC; r < rows; r += RPS) {
+        dst[r * NM + n] = sR[p * RS + l * NPC + n];
+        p += qs;
+        l += rq;
+        if (l >= L1) {
+          l -= L1;
+          ++p;
+        }
+      }
     }
   }
 }

@@ -81,8 +81,14 @@ KernelInfo expand_bwd_info_f32(int L, int normalize, int n_max) {
   // 20 000 environments: staged faster up to 29.8 KB (float32 l_max 8 with 8
   // channels 506 vs 517 us; float64 l_max 4, float32 16 channels l_max 4),
   // direct from 34 KB (float32 l_max 9 712 vs 546 us, l_max 12 1362 vs 773;
-  // float64 l_max 8 1328 vs 678).
-  const int direct = expand_bwd_lds_bytes<T>(L, npc, 32, true) > 32 * 1024 ? 1 : 0;
+  // float64 l_max 8 1328 vs 678).  Padded channels (n_max < npc) copy
+  // their tiles element by element, and float32 staging still paid at
+  // 39-42 KB (12 channels l_max 6 1016 vs 1116 us, 5 channels l_max 10 873
+  // vs 895) but not from 49 KB (l_max 12 1408 vs 1068); float64 lost at
+  // 42 KB (5 channels l_max 6 692 vs 678).  The limit is the largest size
+  // measured to gain, 42240 bytes.
+  const size_t limit = n_max < npc && sizeof(T) == 4 ? 42240 : 32 * 1024;
+  const int direct = expand_bwd_lds_bytes<T>(L, npc, 32, true) > limit ? 1 : 0;
   const int gs = direct ? 64 : 32;
   // one G slice per group where two would not fit (chunks then stop at
   // every environment's end)

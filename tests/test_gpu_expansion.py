@@ -228,8 +228,8 @@ def _check_backward(gx, gR, pts, offs, R, G, l_max, normalize, dt, label=""):
 
 @pytest.mark.parametrize("dt", [torch.float32, torch.float64])
 @pytest.mark.parametrize("l_max,n_max,normalize", [
-    (0, 1, True), (2, 3, False), (4, 8, True), (8, 8, True), (8, 5, False), (8, 16, True), (11, 4, True),
-    (20, 9, True), (28, 12, True)])
+    (0, 1, True), (2, 3, False), (4, 8, True), (6, 12, False), (8, 8, True), (8, 5, False), (8, 16, True),
+    (10, 5, True), (11, 4, True), (20, 9, True), (28, 12, True)])
 def test_expansion_backward_matches_oracle(dt, l_max, n_max, normalize):
     import paper_2302_08381_amd as sph
     print(f"expansion backward {dt} l_max={l_max} n_max={n_max} normalize={normalize}", flush=True)
