@@ -232,12 +232,21 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandParams P) {
         if (i < nv) sv[i] = rb[u];
       }
     } else {
+      // element i = row * NM + ch goes to row * NP + ch; one division per
+      // batch, then running counters (the thread's elements are
+      // kExpandThreads apart)
+      int i = base + tid;
+      int row = i / NM, ch = i - row * NM;
+      const int qs = kExpandThreads / NM, rq = kExpandThreads - qs * NM;
 #pragma unroll
       for (int u = 0; u < RB; ++u) {
-        const int i = base + tid + u * kExpandThreads;
-        if (i < nrv) {
-          const int row = NP == NM ? 0 : i / NM;
-          sR[NP == NM ? i : row * NP + (i - row * NM)] = rb[u / RW][u % RW];
+        if (i < nrv) sR[NP == NM ? i : row * NP + ch] = rb[u / RW][u % RW];
+        i += kExpandThreads;
+        row += qs;
+        ch += rq;
+        if (ch >= NM) {
+          ch -= NM;
+          ++row;
         }
       }
     }
