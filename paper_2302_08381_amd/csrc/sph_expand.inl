@@ -451,7 +451,11 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandParams P) {
 //            and were fetched again (20-30 % slower);
 //   SRC = 2: global memory element by element (loading a degree ahead, as
 //            for SRC = 1, was 1-4 % slower: the second buffer costs
-//            occupancy).
+//            occupancy);
+//   SRC = 3: as SRC = 1 where the channels need padding but still fill
+//            whole 16-byte vectors (NM a multiple of 4 floats or 2
+//            doubles, so every degree's row stays 16-byte aligned): the
+//            vectors past NM are zeros, never loaded or stored.
 template <typename T, int MM, bool NORM, int NPC, int SRC>
 __device__ __forceinline__ void expand_bwd_point(const T* __restrict__ xyz, const T* __restrict__ R,
                                                  const T* __restrict__ sG, T* __restrict__ sRow,
@@ -494,14 +498,25 @@ __device__ __forceinline__ void expand_bwd_point(const T* __restrict__ xyz, cons
   T* gRj = gR != nullptr ? gR + j * (L + 1) * NM : nullptr;
   V ra[NV], rb[NV];
   auto load_r = [&](int l, V (&dst)[NV]) {
+    if constexpr (SRC == 1) {
 #pragma unroll
-    for (int h = 0; h < NV; ++h) dst[h] = reinterpret_cast<const V*>(Rj + l * NPC)[h];
+      for (int h = 0; h < NV; ++h) dst[h] = reinterpret_cast<const V*>(Rj + l * NPC)[h];
+    } else {
+      const V* g = reinterpret_cast<const V*>(Rj + l * NM);
+#pragma unroll
+      for (int h = 0; h < NV; ++h) {
+        V v;
+#pragma unroll
+        for (int u = 0; u < W; ++u) v[u] = T(0);
+        dst[h] = h * W < NM ? g[h] : v;
+      }
+    }
   };
   // degree l; SRC = 1: radial values in rc, the next degree's loads issued
   // into rx first (unconditionally: the last degree loads itself again, so
   // the wait analysis sees one path)
   auto degree = [&](int l, const V (&rc)[NV], V (&rx)[NV]) {
-    if constexpr (SRC == 1) load_r(l < L ? l + 1 : l, rx);
+    if constexpr (SRC == 1 || SRC == 3) load_r(l < L ? l + 1 : l, rx);
     // the degree's derivative coefficients, fetched together before any
     // column: scalar loads share their wait counter with LDS reads, so a
     // fetch next to each column would drain every G read in flight
@@ -524,7 +539,7 @@ __device__ __forceinline__ void expand_bwd_point(const T* __restrict__ xyz, cons
     }
 #pragma unroll
     for (int n = 0; n < NPC; ++n) {
-      if constexpr (SRC == 1) r[n] = rc[n / W][n % W];
+      if constexpr (SRC == 1 || SRC == 3) r[n] = rc[n / W][n % W];
       if constexpr (SRC == 2) r[n] = n < NM ? Rj[l * NM + n] : T(0);
       acc[n] = T(0);
     }
@@ -616,6 +631,16 @@ __device__ __forceinline__ void expand_bwd_point(const T* __restrict__ xyz, cons
           for (int u = 0; u < W; ++u) v[u] = acc[h * W + u];
           reinterpret_cast<V*>(gRj + l * NPC)[h] = v;
         }
+      } else if constexpr (SRC == 3) {
+#pragma unroll
+        for (int h = 0; h < NV; ++h) {
+          if (h * W < NM) {
+            V v;
+#pragma unroll
+            for (int u = 0; u < W; ++u) v[u] = acc[h * W + u];
+            reinterpret_cast<V*>(gRj + l * NM)[h] = v;
+          }
+        }
       } else {
 #pragma unroll
         for (int n = 0; n < NPC; ++n)
@@ -624,7 +649,7 @@ __device__ __forceinline__ void expand_bwd_point(const T* __restrict__ xyz, cons
     }
     copy_row<T, MM>(MM, cur, prev);
   };
-  if constexpr (SRC == 1) load_r(0, ra);
+  if constexpr (SRC == 1 || SRC == 3) load_r(0, ra);
   // two degrees per trip, the radial buffers alternating
 #pragma unroll 1
   for (int l = 0; l <= L; l += 2) {
@@ -786,8 +811,11 @@ __global__ __launch_bounds__(kWave) void k_expand_bwd(ExpandBwdParams P) {
   T* gxyz = static_cast<T*>(P.gxyz);
   T* gR = static_cast<T*>(P.gR);
   // radial rows as whole 16-byte vectors: every padded channel present and
-  // both radial arrays 16-byte aligned (uniform)
-  const bool vec = NM == NPC && aligned16(R) && (gR == nullptr || aligned16(gR));
+  // both radial arrays 16-byte aligned (uniform); vpart: the channels fill
+  // whole vectors short of the padding
+  const bool aligned = aligned16(R) && (gR == nullptr || aligned16(gR));
+  const bool vec = NM == NPC && aligned;
+  const bool vpart = NM % Vec16<T>::n == 0 && aligned;
 
   if (P.status != nullptr && blockIdx.x == 0) {
     bool ok = true;
@@ -887,6 +915,8 @@ __global__ __launch_bounds__(kWave) void k_expand_bwd(ExpandBwdParams P) {
         expand_bwd_point<T, MM, NORM, NPC, 0>(xyz, R, sGj, sR + gl * RS, gxyz, gR, j, L, NM);
       else if (vec)
         expand_bwd_point<T, MM, NORM, NPC, 1>(xyz, R, sGj, nullptr, gxyz, gR, j, L, NM);
+      else if (vpart)
+        expand_bwd_point<T, MM, NORM, NPC, 3>(xyz, R, sGj, nullptr, gxyz, gR, j, L, NM);
       else
         expand_bwd_point<T, MM, NORM, NPC, 2>(xyz, R, sGj, nullptr, gxyz, gR, j, L, NM);
     }

@@ -305,6 +305,30 @@ def test_expansion_backward_through_autograd_matches_torch():
     assert float((gR - ref_R).abs().max()) <= 1e-10 * (1 + float(ref_R.abs().max()))
 
 
+@pytest.mark.parametrize("dt,l_max,n_max", [(torch.float32, 11, 4), (torch.float32, 8, 12), (torch.float64, 6, 6)])
+def test_expansion_backward_partial_vectors(dt, l_max, n_max):
+    """Rows read directly where the channels need padding but fill whole
+    16-byte vectors (16-byte loads, the vectors past n_max zero), and the
+    same inputs one element off a 16-byte boundary (element loads): both
+    against the oracle."""
+    import paper_2302_08381_amd as sph
+    print(f"expansion backward partial vectors {dt} l_max={l_max} n_max={n_max}", flush=True)
+    pts, offs, R = _case([0, 1, 7, 32, 33, 64, 129, 0, 200, 3], l_max, n_max, 960 + l_max + n_max)
+    E, K = offs.size - 1, (l_max + 1) ** 2
+    xyz = to_dev(pts, dt)
+    Rt = to_dev(R, dt)
+    Gt = to_dev(standard_normal((E, n_max, K), 970 + l_max), dt)
+    o = torch.as_tensor(offs, device="cuda")
+    bR = torch.empty(Rt.numel() + 1, dtype=dt, device="cuda")
+    bR[1:] = Rt.flatten()
+    Ru = bR[1:].view(Rt.shape)
+    for Rin, tag in ((Rt, "aligned"), (Ru, "unaligned")):
+        gx, gR = sph.sph_radial_expansion_backward(xyz, o, Rin, Gt, l_max, True)
+        torch.cuda.synchronize()
+        _check_backward(gx, gR, host_points(xyz), offs, Rt.cpu().double().numpy(), Gt.cpu().double().numpy(),
+                        l_max, True, dt, f"{dt} L={l_max} n={n_max} {tag}")
+
+
 def test_expansion_deterministic_and_unaligned_inputs():
     """No atomics: repeated calls are bitwise equal.  Inputs and outputs that
     start at odd element offsets (not 16-byte aligned) give the same results."""
