@@ -185,14 +185,15 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandParams P) {
   };
   T px = T(0), py = T(0), pz = T(0);
   // The radial batch: RB values per thread, as RB / W 16-byte vectors when
-  // the channels need no padding and R is 16-byte aligned (every row is then
-  // a whole number of vectors, the tile a copy of the global block), else
-  // element by element into the padded rows.
+  // the channels fill whole vectors and R is 16-byte aligned (no vector
+  // crosses a row; without padding the tile is a copy of the global block,
+  // with it each vector goes to its row's padded slot), else element by
+  // element into the padded rows.
   using RV = typename Vec16<T>::type;
   constexpr int RW = Vec16<T>::n;
   static_assert(RB % RW == 0, "whole radial vectors");
   constexpr int RBV = RB / RW;
-  const bool rvec = NP == NM && aligned16(R);
+  const bool rvec = NM % RW == 0 && aligned16(R);
   RV rb[RBV];
   auto rload = [&](const T* Rg, int base, int nrv) {  // values base .. base + RB * 128 of the chunk
     if (rvec) {
@@ -226,10 +227,29 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandParams P) {
     if (rvec) {
       RV* sv = reinterpret_cast<RV*>(sR);
       const int nv = nrv / RW;
+      if (NP == NM) {
 #pragma unroll
-      for (int u = 0; u < RBV; ++u) {
-        const int i = base / RW + tid + u * kExpandThreads;
-        if (i < nv) sv[i] = rb[u];
+        for (int u = 0; u < RBV; ++u) {
+          const int i = base / RW + tid + u * kExpandThreads;
+          if (i < nv) sv[i] = rb[u];
+        }
+      } else {
+        // vector i = row * mv + cv goes to row * pv + cv, running counters
+        const int mv = NM / RW, pv = NP / RW;
+        int i = base / RW + tid;
+        int row = i / mv, cv = i - row * mv;
+        const int qs = kExpandThreads / mv, rq = kExpandThreads - qs * mv;
+#pragma unroll
+        for (int u = 0; u < RBV; ++u) {
+          if (i < nv) sv[row * pv + cv] = rb[u];
+          i += kExpandThreads;
+          row += qs;
+          cv += rq;
+          if (cv >= mv) {
+            cv -= mv;
+            ++row;
+          }
+        }
       }
     } else {
       // element i = row * NM + ch goes to row * NP + ch; one division per

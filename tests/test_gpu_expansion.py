@@ -56,6 +56,9 @@ def _check(c, pts, offs, R, l_max, normalize, dt, label=""):
 @pytest.mark.parametrize("l_max,n_max,normalize", [
     (0, 1, True), (1, 3, False), (3, 8, True), (6, 5, True), (8, 8, True), (8, 8, False),
     (12, 4, True), (8, 13, True),
+    # padded channels that fill whole 16-byte vectors (float32 12 of 16;
+    # float64 6 of 8, 12 of 16)
+    (8, 12, True), (6, 6, False),
     # the low-degree kernels whose items are split across otherwise idle
     # threads: into 4 parts (l_max 2, 3 channels), into 2 (l_max 4 with 8
     # channels, l_max 3 with 12)
@@ -68,11 +71,17 @@ def test_expansion_matches_oracle(dt, l_max, n_max, normalize):
     Rt = to_dev(R, dt)
     st = torch.full((1,), -1, dtype=torch.int32, device="cuda")
     c = sph.sph_radial_expansion(xyz, torch.as_tensor(offs, device="cuda"), Rt, l_max, normalize, status=st)
+    # the same radial values one element off a 16-byte boundary (element loads)
+    bR = torch.empty(Rt.numel() + 1, dtype=dt, device="cuda")
+    bR[1:] = Rt.flatten()
+    cu = sph.sph_radial_expansion(xyz, torch.as_tensor(offs, device="cuda"), bR[1:].view(Rt.shape), l_max,
+                                  normalize)
     torch.cuda.synchronize()
     assert int(st.item()) == 0
     # the oracle sees the rounded inputs the kernel saw
-    _check(c, host_points(xyz), offs, Rt.cpu().double().numpy(), l_max, normalize, dt,
-           f"{dt} L={l_max} n={n_max}")
+    for out, tag in ((c, ""), (cu, " unaligned R")):
+        _check(out, host_points(xyz), offs, Rt.cpu().double().numpy(), l_max, normalize, dt,
+               f"{dt} L={l_max} n={n_max}{tag}")
 
 
 @pytest.mark.parametrize("dt,l_max,n_max", [(torch.float32, 5, 8), (torch.float32, 8, 8), (torch.float32, 12, 3),
