@@ -685,13 +685,16 @@ __device__ __forceinline__ void expand_bwd_point(const T* __restrict__ xyz, cons
 
 // Copies of one group's radial tile between global rows [cnt][L+1][NM]
 // (contiguous from src) and LDS rows of stride RS, [L+1][NPC] each (NPC >= NM,
-// the padding channels zero).  VEC (NM == NPC, 16-byte aligned global rows):
-// 16-byte vectors, a batch of them in flight per lane; else single elements,
-// also a batch in flight.  GS lanes of the group take part (lane gl).
-template <typename T, int NPC, int GS, bool VEC>
+// the padding channels zero).  MODE 2 (NM == NPC, 16-byte aligned global
+// rows): the block as contiguous 16-byte vectors, a batch of them in flight
+// per lane.  MODE 1 (NM a whole number of vectors, aligned) and 0 (else):
+// each lane keeps one slot of U channels (a vector, or one element) and
+// walks the tile's rows, a batch in flight.  GS lanes of the group take
+// part (lane gl).
+template <typename T, int NPC, int GS, int MODE>
 __device__ __forceinline__ void expand_tile_in(T* __restrict__ sR, int RS, const T* __restrict__ src, int cnt,
                                                int L, int NM, int gl) {
-  if constexpr (VEC) {
+  if constexpr (MODE == 2) {
     using V = typename Vec16<T>::type;
     constexpr int W = Vec16<T>::n;
     constexpr int NB = 6;
@@ -719,23 +722,33 @@ __device__ __forceinline__ void expand_tile_in(T* __restrict__ sR, int RS, const
         if (i0 + u * GS < nv) *reinterpret_cast<V*>(sR + o[u]) = v[u];
     }
   } else {
-    // lane gl keeps channel n = gl % NPC and walks the rows r = p (L+1) + l
-    // of the tile, GS / NPC rows per step, NB loads in flight; the padding
-    // channels get zeros
-    static_assert(GS % NPC == 0, "whole rows per step");
-    constexpr int RPS = GS / NPC;
+    // lane gl keeps the slot of channels n .. n + U - 1 (n = (gl % SL) U)
+    // and walks the rows r = p (L+1) + l of the tile, GS / SL rows per step,
+    // NB loads in flight; the slots past NM get zeros
+    constexpr int U = MODE == 1 ? Vec16<T>::n : 1;
+    using E = std::conditional_t<U == 1, T, typename Vec16<T>::type>;
+    constexpr int SL = NPC / U;
+    static_assert(GS % SL == 0, "whole rows per step");
+    constexpr int RPS = GS / SL;
     constexpr int NB = 8;
-    const int n = gl % NPC, L1 = L + 1, rows = cnt * L1;
-    int p = (gl / NPC) / L1, l = gl / NPC - p * L1;
+    E zero;
+    if constexpr (U == 1) {
+      zero = T(0);
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) zero[u] = T(0);
+    }
+    const int n = (gl % SL) * U, L1 = L + 1, rows = cnt * L1;
+    int p = (gl / SL) / L1, l = gl / SL - p * L1;
     const int qs = RPS / L1, rq = RPS - qs * L1;
-    for (int r0 = gl / NPC; r0 < rows; r0 += RPS * NB) {
-      T v[NB];
+    for (int r0 = gl / SL; r0 < rows; r0 += RPS * NB) {
+      E v[NB];
       int o[NB];
 #pragma unroll
       for (int u = 0; u < NB; ++u) {
         const int r = r0 + u * RPS;
         o[u] = p * RS + l * NPC + n;
-        v[u] = r < rows && n < NM ? src[r * NM + n] : T(0);
+        v[u] = r < rows && n < NM ? *reinterpret_cast<const E*>(src + r * NM + n) : zero;
         p += qs;
         l += rq;
         if (l >= L1) {
@@ -745,15 +758,15 @@ __device__ __forceinline__ void expand_tile_in(T* __restrict__ sR, int RS, const
       }
 #pragma unroll
       for (int u = 0; u < NB; ++u)
-        if (r0 + u * RPS < rows) sR[o[u]] = v[u];
+        if (r0 + u * RPS < rows) *reinterpret_cast<E*>(sR + o[u]) = v[u];
     }
   }
 }
 
-template <typename T, int NPC, int GS, bool VEC>
+template <typename T, int NPC, int GS, int MODE>
 __device__ __forceinline__ void expand_tile_out(const T* __restrict__ sR, int RS, T* __restrict__ dst, int cnt,
                                                 int L, int NM, int gl) {
-  if constexpr (VEC) {
+  if constexpr (MODE == 2) {
     using V = typename Vec16<T>::type;
     constexpr int W = Vec16<T>::n;
     const int RV = (L + 1) * NPC / W;
@@ -771,14 +784,18 @@ __device__ __forceinline__ void expand_tile_out(const T* __restrict__ sR, int RS
       }
     }
   } else {
-    // the walk of expand_tile_in: channel n = gl % NPC, GS / NPC rows a step
-    constexpr int RPS = GS / NPC;
-    const int n = gl % NPC, L1 = L + 1, rows = cnt * L1;
-    int p = (gl / NPC) / L1, l = gl / NPC - p * L1;
+    // the walk of expand_tile_in: a slot of U channels per lane, GS / SL
+    // rows a step
+    constexpr int U = MODE == 1 ? Vec16<T>::n : 1;
+    using E = std::conditional_t<U == 1, T, typename Vec16<T>::type>;
+    constexpr int SL = NPC / U;
+    constexpr int RPS = GS / SL;
+    const int n = (gl % SL) * U, L1 = L + 1, rows = cnt * L1;
+    int p = (gl / SL) / L1, l = gl / SL - p * L1;
     const int qs = RPS / L1, rq = RPS - qs * L1;
     if (n < NM) {
-      for (int r = gl / NPC; r < rows; r += RPS) {
-        dst[r * NM + n] = sR[p * RS + l * NPC + n];
+      for (int r = gl / SL; r < rows; r += RPS) {
+        *reinterpret_cast<E*>(dst + r * NM + n) = *reinterpret_cast<const E*>(sR + p * RS + l * NPC + n);
         p += qs;
         l += rq;
         if (l >= L1) {
@@ -922,9 +939,11 @@ __global__ __launch_bounds__(kWave) void k_expand_bwd(ExpandBwdParams P) {
       if (active) {
         const T* src = R + j0 * (L + 1) * NM;
         if (vec)
-          expand_tile_in<T, NPC, GS, true>(sR, RS, src, cnt, L, NM, gl);
+          expand_tile_in<T, NPC, GS, 2>(sR, RS, src, cnt, L, NM, gl);
+        else if (vpart)
+          expand_tile_in<T, NPC, GS, 1>(sR, RS, src, cnt, L, NM, gl);
         else
-          expand_tile_in<T, NPC, GS, false>(sR, RS, src, cnt, L, NM, gl);
+          expand_tile_in<T, NPC, GS, 0>(sR, RS, src, cnt, L, NM, gl);
       }
     }
     __syncthreads();
@@ -946,9 +965,11 @@ __global__ __launch_bounds__(kWave) void k_expand_bwd(ExpandBwdParams P) {
         if (active) {
           T* dst = gR + j0 * (L + 1) * NM;
           if (vec)
-            expand_tile_out<T, NPC, GS, true>(sR, RS, dst, cnt, L, NM, gl);
+            expand_tile_out<T, NPC, GS, 2>(sR, RS, dst, cnt, L, NM, gl);
+          else if (vpart)
+            expand_tile_out<T, NPC, GS, 1>(sR, RS, dst, cnt, L, NM, gl);
           else
-            expand_tile_out<T, NPC, GS, false>(sR, RS, dst, cnt, L, NM, gl);
+            expand_tile_out<T, NPC, GS, 0>(sR, RS, dst, cnt, L, NM, gl);
         }
       }
     }

@@ -314,12 +314,14 @@ def test_expansion_backward_through_autograd_matches_torch():
     assert float((gR - ref_R).abs().max()) <= 1e-10 * (1 + float(ref_R.abs().max()))
 
 
-@pytest.mark.parametrize("dt,l_max,n_max", [(torch.float32, 11, 4), (torch.float32, 8, 12), (torch.float64, 6, 6)])
+@pytest.mark.parametrize("dt,l_max,n_max", [(torch.float32, 11, 4), (torch.float32, 8, 12), (torch.float64, 6, 6),
+                                           (torch.float32, 6, 4), (torch.float64, 4, 6)])
 def test_expansion_backward_partial_vectors(dt, l_max, n_max):
-    """Rows read directly where the channels need padding but fill whole
-    16-byte vectors (16-byte loads, the vectors past n_max zero), and the
-    same inputs one element off a 16-byte boundary (element loads): both
-    against the oracle."""
+    """Channels that need padding but fill whole 16-byte vectors, rows read
+    directly (float32 l_max 11 and 8, float64 l_max 6) or staged through the
+    LDS tile (float32 l_max 6, float64 l_max 4) as 16-byte vectors, the
+    vectors past n_max zero; and the same inputs one element off a 16-byte
+    boundary (element loads): both against the oracle."""
     import paper_2302_08381_amd as sph
     print(f"expansion backward partial vectors {dt} l_max={l_max} n_max={n_max}", flush=True)
     pts, offs, R = _case([0, 1, 7, 32, 33, 64, 129, 0, 200, 3], l_max, n_max, 960 + l_max + n_max)
